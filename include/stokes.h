@@ -1,0 +1,215 @@
+/*
+ * stokes.h -- C ABI of the MI355X (gfx950) solver for the staggered Stokes
+ * problem in periodic voxel geometries, by conjugate gradients on the
+ * pressure Schur complement S p = g with S = B A^{-1} B^T and g = B A^{-1} f
+ * (Pimanov, Iliev, Oseledets, Muravleva, arXiv 2307.05266, Sec. 1,
+ * eqs. coupled_matrix, schur_system, schur_rhs; Sec. 3, Algorithm 1).
+ *
+ * Conventions (Sec. 2.1-2.3):
+ *  - The geometry is an N x N x N voxel image, periodic in every direction,
+ *    with the box [0,1]^3 (h = 1/N).  A mask byte is 1 for fluid, 0 for
+ *    solid; voxel (i,j,k) sits at flat index i + N*(j + N*k) (x fastest).
+ *  - Pressure lives at voxel centres (cell arrays of N^3 doubles).
+ *  - Velocity lives on voxel faces: a face array holds 3*N^3 doubles,
+ *    component c (0=x,1=y,2=z) at offset c*N^3; entry (c, X) is the velocity
+ *    on the lower c-face of voxel X, between X - e_c and X.
+ *  - A face is an unknown ("active") when both of its voxels are fluid.  The
+ *    velocity on every other face is zero (no-slip, eq. stokes_bc_noslip).
+ *  - A is the negative velocity Laplacian with the wall half a voxel from
+ *    the face centre (mirrored ghost value); B is the negative divergence
+ *    and B^T the gradient.
+ *  - The body force is uniform; with unit force along an axis the mean
+ *    velocity along that axis is the permeability (eq. darcy_law, L = 1).
+ *
+ * Components: fluid components that cannot carry flow along the force
+ * (no closed path in them winds through the periodic box with a non-zero
+ * component along the force) have zero velocity in the exact solution;
+ * setup removes them, which leaves the solution elsewhere unchanged.  The
+ * pressure of each remaining component is fixed to zero mean (Sec. 2.2).
+ *
+ * Memory and streams: a context owns all of its device memory from setup to
+ * destroy.  All device work of a context runs on one HIP stream (the
+ * default stream unless stokes_set_stream is called).  A context must not be
+ * used from two threads at once; distinct contexts are independent.
+ *
+ * Errors: every call returns a stokes_status.  Negative values are errors;
+ * on an error the context is left as it was before the call unless stated.
+ */
+#ifndef STOKES_H
+#define STOKES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STOKES_OK = 0,
+    STOKES_NOT_CONVERGED = 1,   /* warning: the last iterate is kept and valid */
+    STOKES_E_ARG = -1,          /* invalid argument; no device work was done */
+    STOKES_E_NOMEM = -2,        /* device or host allocation failed */
+    STOKES_E_DEVICE = -3,       /* a HIP call failed */
+    STOKES_E_BREAKDOWN = -4,    /* NaN/Inf or a non-positive curvature (d, S d) <= 0 */
+    STOKES_E_STATE = -5,        /* call out of order (e.g. permeability before solve) */
+    STOKES_E_LIMIT = -6         /* geometry exceeds a documented limit */
+} stokes_status;
+
+typedef enum {
+    STOKES_UZAWA = 0,           /* identity preconditioner (eq. schur_uzawa_prec) */
+    STOKES_SIMPLE = 1           /* B diag(A)^{-1} B^T, applied by an inner PCG solve */
+} stokes_precond;
+
+/* Operators for stokes_apply / stokes_apply_device. */
+typedef enum {
+    STOKES_OP_A = 0,            /* faces -> faces: A u */
+    STOKES_OP_B = 1,            /* faces -> cells: B u (negative divergence) */
+    STOKES_OP_BT = 2,           /* cells -> faces: B^T p (gradient) */
+    STOKES_OP_SHAT = 3,         /* cells -> cells: B diag(A)^{-1} B^T p */
+    STOKES_OP_DIAG_A = 4,       /* -> faces: diag(A) on active faces (input ignored) */
+    STOKES_OP_DIAG_SHAT = 5,    /* -> cells: diag(B diag(A)^{-1} B^T) (input ignored) */
+    STOKES_OP_PROJECT = 6,      /* cells -> cells: remove each component's mean */
+    STOKES_OP_S = 7             /* cells -> cells: B A^{-1} B^T p with an inner solve at eps_A */
+} stokes_op;
+
+/* setup flags */
+#define STOKES_KEEP_ALL_COMPONENTS 0x1u  /* do not remove non-conducting components */
+
+/* report flags */
+#define STOKES_FLAG_NO_FLOW        0x1u  /* no conducting fluid: k = 0 exactly */
+#define STOKES_FLAG_ZERO_RHS       0x2u  /* g = 0: the pressure is zero, no outer iteration */
+#define STOKES_FLAG_INNER_MAXIT    0x4u  /* an inner solve stopped at its iteration cap */
+
+typedef struct stokes_ctx stokes_ctx;
+
+typedef struct {
+    int status;                 /* stokes_status of the solve */
+    unsigned flags;             /* STOKES_FLAG_* */
+    int outer_iters;            /* S applications inside the outer loop */
+    int inner_A_iters;          /* total inner iterations with A (including g) */
+    int inner_S_iters;          /* total inner iterations with the SIMPLE matrix */
+    int n_components;           /* fluid components of the mask as given */
+    int n_components_kept;      /* components that carry flow */
+    double k_hat;               /* permeability, non-dimensional (L = 1): k_vox / N^2 */
+    double k_vox;               /* permeability in voxel units (h = 1) */
+    double mean_u[3];           /* box-mean velocity, voxel units */
+    double rel_res;             /* ||r_k|| / ||r_0||, r = g - S p */
+    double rel_res_prec;        /* ||z_k|| / ||z_0||, z = preconditioned residual */
+    double r0_norm;             /* ||g|| */
+    double div_norm;            /* ||B u|| of the returned velocity */
+    double cond_est;            /* Lanczos estimate from the CG coefficients */
+    double ritz_min, ritz_max;
+    double porosity;            /* fluid fraction of the mask as given */
+    double porosity_effective;  /* after removing non-conducting components */
+    double stv_ratio;           /* surface-to-volume ratio (eq. s-t-v-ration), a fraction */
+    double seconds;             /* wall time of the solve */
+} stokes_report;
+
+/*
+ * stokes_setup -- build a context for one geometry (Sec. 2.1-2.2).
+ *   ctx    out: new context; untouched on error.
+ *   mask   host pointer to N^3 bytes (1 = fluid, 0 = solid), x fastest;
+ *          read during the call only (it is copied).
+ *   N      voxels per side, 2 <= N <= 800.
+ *   force  host pointer to 3 doubles, the uniform body force (finite, not all 0).
+ * Returns STOKES_E_ARG for a bad N, a mask byte other than 0/1, or a bad
+ * force; STOKES_E_LIMIT when more than 2048 conducting components remain.
+ * A geometry without conducting fluid is valid (its permeability is 0).
+ */
+stokes_status stokes_setup(stokes_ctx **ctx, const uint8_t *mask, int N, const double force[3]);
+
+/* As stokes_setup, with flags (STOKES_KEEP_ALL_COMPONENTS: keep every fluid
+ * component; each then carries its own pressure constant). */
+stokes_status stokes_setup_ex(stokes_ctx **ctx, const uint8_t *mask, int N, const double force[3],
+                              unsigned flags);
+
+/*
+ * stokes_preprocess -- the host-only part of stokes_setup (Sec. 2.1-2.2,
+ * eqs. porosity, s-t-v-ration, surface_area); needs no GPU.
+ *   mask, N, force, flags  as for stokes_setup_ex.
+ *   counts  out, 6 values: fluid voxels (as given), fluid voxels kept,
+ *           surface voxels, components (as given), components kept, 0.
+ *   fluid   out, N^3 bytes or NULL: 1 where fluid is kept.
+ *   label   out, N^3 int32 or NULL: kept-component id, -1 elsewhere
+ *           (components numbered by their lowest voxel index).
+ * Returns STOKES_E_ARG as stokes_setup does.
+ */
+stokes_status stokes_preprocess(const uint8_t *mask, int N, const double force[3], unsigned flags,
+                                int64_t counts[6], uint8_t *fluid, int32_t *label);
+
+/* Run the context's device work on this HIP stream (hipStream_t; NULL =
+ * the default stream).  The caller keeps ownership of the stream. */
+stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
+
+/*
+ * stokes_set_option -- solver options (Sec. 3.1-3.2 stopping criteria):
+ *   "eps_A"       inner relative tolerance for A (default 1e-12)
+ *   "eps_S"       inner relative tolerance for the SIMPLE matrix (default 1e-12)
+ *   "max_outer"   outer iteration cap (default 5000)
+ *   "max_inner"   inner iteration cap per solve (default 100000)
+ *   "stop_prec"   0: stop on ||r||/||r0|| (default); 1: on ||z||/||z0||
+ *                 (the preconditioned norm of Algorithm 1)
+ *   "check_every" inner iterations queued between convergence checks (default 0 = adaptive)
+ *   "kernel_timing" 1: time every launch of the A-stencil kernel with HIP events
+ *   "true_velocity" 1: after the solve, recompute u = A^{-1}(f - B^T p)
+ * Unknown keys or out-of-range values give STOKES_E_ARG.
+ */
+stokes_status stokes_set_option(stokes_ctx *ctx, const char *key, double value);
+
+/*
+ * stokes_solve -- CG on S p = g (Algorithm 1, with r = g - S p), starting
+ * from p = 0, with the chosen preconditioner, until the relative residual
+ * (see "stop_prec") is below tol.  report may be NULL.
+ * Returns STOKES_OK, STOKES_NOT_CONVERGED (iteration cap; last iterate kept),
+ * STOKES_E_BREAKDOWN, STOKES_E_ARG (tol not positive and finite).
+ */
+stokes_status stokes_solve(stokes_ctx *ctx, stokes_precond precond, double tol, stokes_report *report);
+
+/* Permeability of the last solve along the force, non-dimensional (Sec. 2.3):
+ * k_hat = <u . f> / |f|^2 / N^2.  STOKES_E_STATE before a solve. */
+stokes_status stokes_permeability(stokes_ctx *ctx, double *k_hat);
+
+/* Report of the last solve (STOKES_E_STATE before a solve). */
+stokes_status stokes_get_report(stokes_ctx *ctx, stokes_report *report);
+
+/* Per outer iteration k = 1..n of the last solve, 8 doubles each:
+ * ||r_k||/||r_0||, ||z_k||/||z_0||, k_hat(u_k), inner A iters, inner S iters,
+ * alpha_{k-1}, beta_{k-1} (0 if the loop stopped first), 0.
+ * Writes min(n, cap) rows to out (host), returns n in *n_out. */
+stokes_status stokes_history(stokes_ctx *ctx, double *out, int cap, int *n_out);
+
+/* Copy the last solution to host memory: p (N^3, zero-mean per component,
+ * 0 in solid) and u (3*N^3, 0 on inactive faces).  Either may be NULL. */
+stokes_status stokes_get_fields(stokes_ctx *ctx, double *p, double *u);
+
+/* Apply one operator (stokes_op) to a host field, writing a host field.
+ * Entries of `in` on inactive faces / solid cells are treated as 0.
+ * Sizes: faces 3*N^3 doubles, cells N^3 doubles. */
+stokes_status stokes_apply(stokes_ctx *ctx, int op, const double *in, double *out);
+
+/* As stokes_apply, with device pointers; runs on the context's stream and
+ * returns without waiting for it. */
+stokes_status stokes_apply_device(stokes_ctx *ctx, int op, const double *in, double *out);
+
+/* info[0..11]: N, fluid voxels (as given), fluid voxels kept, surface voxels,
+ * components (as given), components kept, active x/y/z faces (3 values),
+ * device bytes held, 0, 0. */
+stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
+
+/* Time spent in the A-stencil kernel over the solves since the last call,
+ * measured with HIP events on the context's stream when "kernel_timing" is
+ * on: total milliseconds, number of launches, and cells swept per launch. */
+stokes_status stokes_kernel_timing(stokes_ctx *ctx, double *ms_total, int64_t *launches,
+                                   int64_t *cells_per_launch);
+
+/* Free everything the context holds.  NULL is ignored. */
+void stokes_destroy(stokes_ctx *ctx);
+
+/* Static string naming a status. */
+const char *stokes_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOKES_H */

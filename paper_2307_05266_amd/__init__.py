@@ -1,0 +1,38 @@
+"""MI355X-native solver for Stokes flow in periodic voxel geometries.
+
+Conjugate gradients on the pressure Schur complement S = B A^{-1} B^T of the
+staggered (MAC) discretization, with the Uzawa (identity) or SIMPLE
+(B diag(A)^{-1} B^T) preconditioner, computing permeabilities of porous media
+(Pimanov, Iliev, Oseledets, Muravleva, arXiv 2307.05266).  The solver is a
+HIP library for gfx950 behind a C ABI (include/stokes.h); this package holds
+its sources (csrc/), the build script and a thin ctypes binding.
+"""
+
+from .stokes import (  # noqa: F401
+    Stokes,
+    StokesError,
+    load,
+    stokes_apply,
+    stokes_apply_device,
+    stokes_destroy,
+    stokes_get_fields,
+    stokes_history,
+    stokes_info,
+    stokes_kernel_timing,
+    stokes_permeability,
+    stokes_preprocess,
+    stokes_set_option,
+    stokes_set_stream,
+    stokes_setup,
+    stokes_solve,
+    STOKES_UZAWA,
+    STOKES_SIMPLE,
+    STOKES_OP_A,
+    STOKES_OP_B,
+    STOKES_OP_BT,
+    STOKES_OP_SHAT,
+    STOKES_OP_DIAG_A,
+    STOKES_OP_DIAG_SHAT,
+    STOKES_OP_PROJECT,
+    STOKES_OP_S,
+)

@@ -1,0 +1,822 @@
+// C ABI and host driver of the MI355X Stokes Schur-complement solver.
+//
+// The outer loop is Algorithm 1 of Pimanov et al. (arXiv 2307.05266, Sec. 3.1)
+// written as standard preconditioned CG on S p = g (residual r = g - S p),
+// with S d = B A^{-1} B^T d applied through an inner Jacobi-PCG solve with A
+// and, for the SIMPLE preconditioner (eq. schur_uzawa_prec), z = Shat^+ r by an
+// inner Jacobi-PCG solve with Shat = B diag(A)^{-1} B^T (Sec. 3.2).  Inner
+// loops keep their scalars on the device; the host only polls a small state
+// block every few iterations.  Outer scalars are formed on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stokes.h"
+#include "geometry.h"
+#include "kernels.h"
+
+using namespace stokes;
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return STOKES_E_DEVICE;   \
+    } while (0)
+
+#define ST_TRY(expr)                                    \
+    do {                                                \
+        stokes_status _s = (expr);                      \
+        if (_s < 0) return _s;                          \
+    } while (0)
+
+namespace {
+
+constexpr int kMaxN = 800;
+constexpr int kCompBlocks = 256;
+
+struct HostState {
+    CgState s;
+};
+
+}  // namespace
+
+struct stokes_ctx {
+    int N = 0;
+    int64_t n3 = 0;
+    double force[3] = {0, 0, 0};
+    unsigned setup_flags = 0;
+    hipStream_t stream = nullptr;
+
+    // geometry summary
+    int64_t nfluid_in = 0, nfluid = 0, nsurf = 0;
+    int ncomp_all = 0, ncomp_kept = 0;
+    int64_t nface[3] = {0, 0, 0};
+
+    Sweep sw{};
+    int wpr = 0;            // bitmask words per x-row
+
+    // device memory
+    uint32_t* bits = nullptr;
+    uint8_t* code = nullptr;
+    uint16_t* label = nullptr;     // only with more than one component
+    double* comp_count = nullptr;  // [K]
+    double* comp_part = nullptr;   // [kCompBlocks][K]
+    double* comp_mean = nullptr;   // [K]
+    double *fx = nullptr, *fr = nullptr, *fd = nullptr, *fq = nullptr, *u = nullptr;   // faces
+    double *p = nullptr, *r = nullptr, *zs = nullptr, *d = nullptr, *q = nullptr;     // cells
+    double *sr = nullptr, *sd = nullptr, *sq = nullptr;                               // cells (SIMPLE solve)
+    CgState* cg = nullptr;         // [0] A, [1] SIMPLE
+    Reduce red{};
+    std::vector<void*> allocations;
+    int64_t device_bytes = 0;
+    CgState* host_state = nullptr; // pinned
+    double* host_out = nullptr;    // pinned [8]
+
+    // options
+    double eps_A = 1e-12, eps_S = 1e-12;
+    int max_outer = 5000, max_inner = 100000;
+    int stop_prec = 0, check_every = 0, true_velocity = 0;
+    bool timing = false;
+
+    // adaptive polling
+    int last_it[2] = {0, 0};
+
+    // results
+    bool have_solution = false;
+    stokes_report rep{};
+    std::vector<double> hist;
+
+    // kernel timing
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double timing_ms = 0.0;
+    int64_t timing_launches = 0;
+};
+
+namespace {
+
+Sweep make_sweep(int N) {
+    Sweep s{};
+    s.N = N;
+    s.bxlog = N >= 64 ? 6 : 5;
+    const int bx = 1 << s.bxlog, by = kBlock >> s.bxlog;
+    s.gx = (N + bx - 1) / bx;
+    s.gy = (N + by - 1) / by;
+    const int cols = s.gx * s.gy;
+    int gz = std::max(1, std::min(N, (2048 + cols - 1) / cols));
+    s.lz = (N + gz - 1) / gz;
+    s.gz = (N + s.lz - 1) / s.lz;
+    s.nblk = s.gx * s.gy * s.gz;
+    return s;
+}
+
+template <class T>
+stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
+    void* m = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&m, bytes) != hipSuccess) return STOKES_E_NOMEM;
+    c->allocations.push_back(m);
+    c->device_bytes += (int64_t)bytes;
+    *ptr = static_cast<T*>(m);
+    return STOKES_OK;
+}
+
+void release(stokes_ctx* c) {
+    for (void* m : c->allocations) (void)hipFree(m);
+    c->allocations.clear();
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    if (c->host_state) (void)hipHostFree(c->host_state);
+    if (c->host_out) (void)hipHostFree(c->host_out);
+    c->host_state = nullptr;
+    c->host_out = nullptr;
+}
+
+dim3 grid_of(const Sweep& s) { return dim3((unsigned)s.nblk); }
+
+// ---- inner solves -----------------------------------------------------------
+stokes_status time_begin(stokes_ctx* c) {
+    if (!c->timing) return STOKES_OK;
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int q = 0; q < 256; ++q) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+    }
+    HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
+    return STOKES_OK;
+}
+
+stokes_status time_end(stokes_ctx* c) {
+    if (!c->timing) return STOKES_OK;
+    HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    c->ev_used += 2;
+    return STOKES_OK;
+}
+
+stokes_status collect_timing(stokes_ctx* c) {
+    if (!c->timing || c->ev_used == 0) return STOKES_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]));
+        c->timing_ms += ms;
+        c->timing_launches += 1;
+    }
+    c->ev_used = 0;
+    return STOKES_OK;
+}
+
+stokes_status read_state(stokes_ctx* c, int which, CgState* out) {
+    HIP_TRY(hipMemcpyAsync(c->host_state, c->cg + which, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = *c->host_state;
+    return STOKES_OK;
+}
+
+int first_batch(stokes_ctx* c, int which) {
+    if (c->check_every > 0) return c->check_every;
+    return c->last_it[which] > 0 ? std::max(1, c->last_it[which] - 1) : 16;
+}
+
+int next_batch(stokes_ctx* c) { return c->check_every > 0 ? c->check_every : 4; }
+
+// Solve A x = b on the faces (b == nullptr: the uniform force).  x -> c->fx.
+stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    const Sweep& s = c->sw;
+    CgState* st = c->cg + 0;
+    hipLaunchKernelGGL(k_cgA_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0], c->force[1],
+                       c->force[2], c->fx, c->fr, c->fd, st, c->red, eps, c->max_inner);
+    HIP_TRY(hipGetLastError());
+    int batch = first_batch(c, 0);
+    CgState h{};
+    for (;;) {
+        for (int t = 0; t < batch; ++t) {
+            ST_TRY(time_begin(c));
+            hipLaunchKernelGGL(k_cgA_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fd, c->fq, st,
+                               c->red);
+            ST_TRY(time_end(c));
+            hipLaunchKernelGGL(k_cgA_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fx, c->fr, c->fd,
+                               c->fq, st, c->red);
+            hipLaunchKernelGGL(k_cgA_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->fd, st);
+        }
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(c, 0, &h));
+        if (h.done) break;
+        batch = next_batch(c);
+    }
+    c->last_it[0] = h.it;
+    *iters = h.it;
+    *status = h.status;
+    return STOKES_OK;
+}
+
+// Solve Shat x = b on the cells (b already projected).  x -> c->zs.
+stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    const Sweep& s = c->sw;
+    CgState* st = c->cg + 1;
+    hipLaunchKernelGGL(k_cgS_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->zs, c->sr, c->sd, st,
+                       c->red, eps, c->max_inner);
+    HIP_TRY(hipGetLastError());
+    int batch = first_batch(c, 1);
+    CgState h{};
+    for (;;) {
+        for (int t = 0; t < batch; ++t) {
+            hipLaunchKernelGGL(k_cgS_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->sd, c->sq, st,
+                               c->red);
+            hipLaunchKernelGGL(k_cgS_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->zs, c->sr, c->sd,
+                               c->sq, st, c->red);
+            hipLaunchKernelGGL(k_cgS_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->sr, c->sd, st);
+        }
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(c, 1, &h));
+        if (h.done) break;
+        batch = next_batch(c);
+    }
+    c->last_it[1] = h.it;
+    *iters = h.it;
+    *status = h.status;
+    return STOKES_OK;
+}
+
+// ---- outer-loop helpers ---------------------------------------------------------
+stokes_status project(stokes_ctx* c, double* x) {
+    const int K = c->ncomp_kept;
+    if (K == 0) return STOKES_OK;
+    const int64_t chunk = ((c->n3 + kCompBlocks - 1) / kCompBlocks + 255) / 256 * 256;
+    const int nb = (int)((c->n3 + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_comp_sum, dim3(nb), dim3(kBlock), (size_t)kWaves * K * sizeof(double), c->stream, x,
+                       c->label, c->bits, c->N, c->wpr, c->n3, K, chunk, c->comp_part);
+    hipLaunchKernelGGL(k_comp_mean, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, c->comp_part, nb, K,
+                       c->comp_count, c->comp_mean);
+    const int subblocks = (int)std::min<int64_t>(4096, (c->n3 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_comp_sub, dim3(subblocks), dim3(kBlock), 0, c->stream, x, c->label, c->bits, c->N, c->wpr,
+                       c->n3, c->comp_mean);
+    HIP_TRY(hipGetLastError());
+    return STOKES_OK;
+}
+
+stokes_status dots(stokes_ctx* c, const double* a0, const double* b0, const double* a1, const double* b1,
+                   const double* a2, const double* b2, double out[3]) {
+    hipLaunchKernelGGL(k_dots, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, a0, b0, a1, b1, a2, b2, c->red);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->host_out, c->red.out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out[0] = c->host_out[0];
+    out[1] = c->host_out[1];
+    out[2] = c->host_out[2];
+    return STOKES_OK;
+}
+
+stokes_status face_sums(stokes_ctx* c, const double* u, double out[3]) {
+    hipLaunchKernelGGL(k_face_sums, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, u, c->red);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->host_out, c->red.out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out[0] = c->host_out[0];
+    out[1] = c->host_out[1];
+    out[2] = c->host_out[2];
+    return STOKES_OK;
+}
+
+// permeability (voxel units) along the force from face sums
+double kvox_of(const stokes_ctx* c, const double sums[3], double mean[3]) {
+    double f2 = 0.0, fu = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        mean[a] = sums[a] / (double)c->n3;
+        f2 += c->force[a] * c->force[a];
+        fu += c->force[a] * mean[a];
+    }
+    return fu / f2;
+}
+
+// Extreme eigenvalues of the CG tridiagonal (Lanczos, Saad Sec. 6.7.3) by
+// bisection on Sturm sequence counts.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b2, double x) {
+    int cnt = 0;
+    double qv = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        qv = a[i] - x - (i > 0 ? b2[i - 1] / qv : 0.0);
+        if (qv == 0.0) qv = -1e-300;
+        if (qv < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+void lanczos_extremes(const std::vector<double>& alpha, const std::vector<double>& beta, double* lo, double* hi) {
+    const size_t k = alpha.size();
+    *lo = *hi = std::nan("");
+    if (k == 0) return;
+    std::vector<double> a(k), b2(k > 0 ? k - 1 : 0);
+    for (size_t j = 0; j < k; ++j) {
+        a[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+        if (j > 0) b2[j - 1] = beta[j - 1] / (alpha[j - 1] * alpha[j - 1]);
+    }
+    double gl = 1e300, gh = -1e300;
+    for (size_t j = 0; j < k; ++j) {
+        double rad = (j > 0 ? std::sqrt(b2[j - 1]) : 0.0) + (j + 1 < k ? std::sqrt(b2[j]) : 0.0);
+        gl = std::min(gl, a[j] - rad);
+        gh = std::max(gh, a[j] + rad);
+    }
+    auto kth = [&](int idx) {  // idx-th smallest eigenvalue, 0-based
+        double l = gl, h = gh;
+        for (int it = 0; it < 200; ++it) {
+            double m = 0.5 * (l + h);
+            if (sturm_count(a, b2, m) > idx) h = m;
+            else l = m;
+            if (h - l <= 1e-14 * std::max(std::fabs(l), std::fabs(h))) break;
+        }
+        return 0.5 * (l + h);
+    };
+    *lo = kth(0);
+    *hi = kth((int)k - 1);
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* stokes_status_str(int s) {
+    switch (s) {
+    case STOKES_OK: return "ok";
+    case STOKES_NOT_CONVERGED: return "not converged";
+    case STOKES_E_ARG: return "invalid argument";
+    case STOKES_E_NOMEM: return "out of memory";
+    case STOKES_E_DEVICE: return "device error";
+    case STOKES_E_BREAKDOWN: return "breakdown";
+    case STOKES_E_STATE: return "invalid state";
+    case STOKES_E_LIMIT: return "limit exceeded";
+    default: return "unknown";
+    }
+}
+
+static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
+    Geometry g;
+    preprocess(mask, c->N, c->force, (c->setup_flags & STOKES_KEEP_ALL_COMPONENTS) != 0, g);
+    c->nfluid_in = g.nfluid_in;
+    c->nfluid = g.nfluid;
+    c->nsurf = g.nsurf;
+    c->ncomp_all = g.ncomp_all;
+    c->ncomp_kept = g.ncomp_kept;
+    if (g.ncomp_kept > kMaxCompLds) return STOKES_E_LIMIT;
+
+    const int N = c->N;
+    const int64_t n3 = c->n3;
+    c->sw = make_sweep(N);
+    if (c->sw.nblk > kMaxBlocks) return STOKES_E_LIMIT;
+    c->wpr = (N + 31) / 32;
+
+    // remaining-fluid bitmask
+    std::vector<uint32_t> bits((size_t)N * N * c->wpr, 0u);
+    for (int64_t row = 0; row < (int64_t)N * N; ++row)
+        for (int i = 0; i < N; ++i)
+            if (g.fluid[row * N + i]) bits[row * c->wpr + (i >> 5)] |= 1u << (i & 31);
+
+    const int K = std::max(1, g.ncomp_kept);
+    ST_TRY(dev_alloc(c, &c->bits, bits.size()));
+    ST_TRY(dev_alloc(c, &c->code, (size_t)n3));
+    ST_TRY(dev_alloc(c, &c->comp_count, (size_t)K));
+    ST_TRY(dev_alloc(c, &c->comp_part, (size_t)kCompBlocks * K));
+    ST_TRY(dev_alloc(c, &c->comp_mean, (size_t)K));
+    if (g.ncomp_kept > 1) ST_TRY(dev_alloc(c, &c->label, (size_t)n3));
+    for (double** f : {&c->fx, &c->fr, &c->fd, &c->fq, &c->u}) ST_TRY(dev_alloc(c, f, (size_t)(3 * n3)));
+    for (double** v : {&c->p, &c->r, &c->zs, &c->d, &c->q, &c->sr, &c->sd, &c->sq})
+        ST_TRY(dev_alloc(c, v, (size_t)n3));
+    ST_TRY(dev_alloc(c, &c->cg, 2));
+    ST_TRY(dev_alloc(c, &c->red.part, (size_t)kMaxParts * kMaxBlocks));
+    ST_TRY(dev_alloc(c, &c->red.ticket, 1));
+    ST_TRY(dev_alloc(c, &c->red.out, 8));
+    if (hipHostMalloc((void**)&c->host_state, sizeof(CgState)) != hipSuccess) return STOKES_E_NOMEM;
+    if (hipHostMalloc((void**)&c->host_out, 8 * sizeof(double)) != hipSuccess) return STOKES_E_NOMEM;
+
+    std::vector<double> counts(K, 0.0);
+    for (int q = 0; q < g.ncomp_kept; ++q) counts[q] = (double)g.comp_size[q];
+    HIP_TRY(hipMemcpyAsync(c->bits, bits.data(), bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->comp_count, counts.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (c->label)
+        HIP_TRY(hipMemcpyAsync(c->label, g.label.data(), (size_t)n3 * sizeof(uint16_t), hipMemcpyHostToDevice,
+                               c->stream));
+    HIP_TRY(hipMemsetAsync(c->red.ticket, 0, sizeof(unsigned), c->stream));
+    HIP_TRY(hipMemsetAsync(c->p, 0, (size_t)n3 * sizeof(double), c->stream));
+    HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+    hipLaunchKernelGGL(k_face_codes, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->bits, c->wpr, c->code);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the host vectors above go out of scope
+
+    // active faces per direction (host count from the remaining fluid)
+    for (int a = 0; a < 3; ++a) c->nface[a] = 0;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const int64_t X = i + (int64_t)N * (j + (int64_t)N * k);
+                if (!g.fluid[X]) continue;
+                if (g.fluid[((i + N - 1) % N) + (int64_t)N * (j + (int64_t)N * k)]) c->nface[0]++;
+                if (g.fluid[i + (int64_t)N * (((j + N - 1) % N) + (int64_t)N * k)]) c->nface[1]++;
+                if (g.fluid[i + (int64_t)N * (j + (int64_t)N * ((k + N - 1) % N))]) c->nface[2]++;
+            }
+    return STOKES_OK;
+}
+
+static stokes_status check_inputs(const uint8_t* mask, int N, const double force[3], unsigned flags) {
+    if (!mask || !force) return STOKES_E_ARG;
+    if (N < 2 || N > kMaxN) return STOKES_E_ARG;
+    if (flags & ~STOKES_KEEP_ALL_COMPONENTS) return STOKES_E_ARG;
+    double f2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(force[a])) return STOKES_E_ARG;
+        f2 += force[a] * force[a];
+    }
+    if (!(f2 > 0.0) || !std::isfinite(f2)) return STOKES_E_ARG;
+    const int64_t n3 = (int64_t)N * N * N;
+    for (int64_t x = 0; x < n3; ++x)
+        if (mask[x] > 1) return STOKES_E_ARG;
+    return STOKES_OK;
+}
+
+stokes_status stokes_preprocess(const uint8_t* mask, int N, const double force[3], unsigned flags, int64_t counts[6],
+                                uint8_t* fluid, int32_t* label) {
+    if (!counts) return STOKES_E_ARG;
+    ST_TRY(check_inputs(mask, N, force, flags));
+    try {
+        Geometry g;
+        preprocess(mask, N, force, (flags & STOKES_KEEP_ALL_COMPONENTS) != 0, g);
+        counts[0] = g.nfluid_in;
+        counts[1] = g.nfluid;
+        counts[2] = g.nsurf;
+        counts[3] = g.ncomp_all;
+        counts[4] = g.ncomp_kept;
+        counts[5] = 0;
+        if (fluid) std::memcpy(fluid, g.fluid.data(), (size_t)g.n3);
+        if (label) {
+            if (g.label.empty() && g.ncomp_kept > 0) return STOKES_E_LIMIT;
+            for (int64_t x = 0; x < g.n3; ++x)
+                label[x] = g.ncomp_kept == 0 ? -1 : (g.label[x] == 0xFFFF ? -1 : (int32_t)g.label[x]);
+        }
+    } catch (const std::bad_alloc&) {
+        return STOKES_E_NOMEM;
+    }
+    return STOKES_OK;
+}
+
+stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, const double force[3], unsigned flags) {
+    if (!out) return STOKES_E_ARG;
+    ST_TRY(check_inputs(mask, N, force, flags));
+    const int64_t n3 = (int64_t)N * N * N;
+
+    stokes_ctx* c = new (std::nothrow) stokes_ctx();
+    if (!c) return STOKES_E_NOMEM;
+    c->N = N;
+    c->n3 = n3;
+    for (int a = 0; a < 3; ++a) c->force[a] = force[a];
+    c->setup_flags = flags;
+    stokes_status st;
+    try {
+        st = setup_impl(c, mask);
+    } catch (const std::bad_alloc&) {
+        st = STOKES_E_NOMEM;
+    }
+    if (st < 0) {
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return STOKES_OK;
+}
+
+stokes_status stokes_setup(stokes_ctx** out, const uint8_t* mask, int N, const double force[3]) {
+    return stokes_setup_ex(out, mask, N, force, 0u);
+}
+
+stokes_status stokes_set_stream(stokes_ctx* c, void* stream) {
+    if (!c) return STOKES_E_ARG;
+    c->stream = (hipStream_t)stream;
+    return STOKES_OK;
+}
+
+stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
+    if (!c || !key || !std::isfinite(v)) return STOKES_E_ARG;
+    const std::string k(key);
+    if (k == "eps_A") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_A = v; }
+    else if (k == "eps_S") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_S = v; }
+    else if (k == "max_outer") { if (v < 1 || v > 1e7) return STOKES_E_ARG; c->max_outer = (int)v; }
+    else if (k == "max_inner") { if (v < 1 || v > 1e8) return STOKES_E_ARG; c->max_inner = (int)v; }
+    else if (k == "stop_prec") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->stop_prec = (int)v; }
+    else if (k == "check_every") { if (v < 0 || v > 4096) return STOKES_E_ARG; c->check_every = (int)v; }
+    else if (k == "kernel_timing") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->timing = v != 0.0; }
+    else if (k == "true_velocity") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->true_velocity = (int)v; }
+    else return STOKES_E_ARG;
+    return STOKES_OK;
+}
+
+static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double tol) {
+    stokes_report& R = c->rep;
+    const Sweep& s = c->sw;
+    const int64_t n3 = c->n3;
+    R = stokes_report{};
+    R.n_components = c->ncomp_all;
+    R.n_components_kept = c->ncomp_kept;
+    R.porosity = (double)c->nfluid_in / (double)n3;
+    R.porosity_effective = (double)c->nfluid / (double)n3;
+    R.stv_ratio = c->nfluid_in ? (double)c->nsurf / (double)c->nfluid_in : 0.0;
+    R.cond_est = R.ritz_min = R.ritz_max = std::nan("");
+    c->hist.clear();
+    c->have_solution = false;
+    const double N2 = (double)c->N * (double)c->N;
+
+    HIP_TRY(hipMemsetAsync(c->p, 0, (size_t)n3 * sizeof(double), c->stream));
+    if (c->nfluid == 0) {
+        HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        R.flags |= STOKES_FLAG_NO_FLOW;
+        R.status = STOKES_OK;
+        c->have_solution = true;
+        return STOKES_OK;
+    }
+
+    int itA = 0, itS = 0, stA = 0, stS = 0;
+    int64_t totA = 0, totS = 0;
+    int status = STOKES_OK;
+    auto note_inner = [&](int st) {
+        if (st == -4) status = STOKES_E_BREAKDOWN;
+        else if (st == 1) R.flags |= STOKES_FLAG_INNER_MAXIT;
+    };
+
+    // u0 = A^{-1} f
+    ST_TRY(cg_A(c, nullptr, c->eps_A, &itA, &stA));
+    totA += itA;
+    note_inner(stA);
+    std::swap(c->u, c->fx);
+    // r0 = g - S 0 = B u0
+    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
+    HIP_TRY(hipGetLastError());
+    ST_TRY(project(c, c->r));
+    double* z = c->r;
+    if (precond == STOKES_SIMPLE) {
+        ST_TRY(cg_S(c, c->r, c->eps_S, &itS, &stS));
+        totS += itS;
+        note_inner(stS);
+        ST_TRY(project(c, c->zs));
+        z = c->zs;
+    }
+    double dd[3];
+    ST_TRY(dots(c, c->r, z, c->r, c->r, z, z, dd));
+    double rz = dd[0];
+    const double r0 = std::sqrt(dd[1]), z0 = std::sqrt(dd[2]);
+    R.r0_norm = r0;
+    HIP_TRY(hipMemcpyAsync(c->d, z, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+
+    std::vector<double> alphas, betas;
+    int k = 0;
+    double rel = 0.0, relz = 0.0;
+    if (!(r0 > 0.0)) {
+        R.flags |= STOKES_FLAG_ZERO_RHS;
+    } else {
+        while (status >= 0) {
+            if (k >= c->max_outer) {
+                status = STOKES_NOT_CONVERGED;
+                break;
+            }
+            const int64_t a0 = totA, s0 = totS;
+            // q = S d = B A^{-1} B^T d
+            hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->d, c->fr);
+            HIP_TRY(hipGetLastError());
+            ST_TRY(cg_A(c, c->fr, c->eps_A, &itA, &stA));
+            totA += itA;
+            note_inner(stA);
+            hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx, c->q);
+            HIP_TRY(hipGetLastError());
+            double dq3[3];
+            ST_TRY(dots(c, c->d, c->q, nullptr, nullptr, nullptr, nullptr, dq3));
+            const double dq = dq3[0];
+            if (!(dq > 0.0) || !std::isfinite(dq)) {
+                status = STOKES_E_BREAKDOWN;
+                break;
+            }
+            const double alpha = rz / dq;
+            hipLaunchKernelGGL(k_outer_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->p, c->r, c->d, c->q,
+                               alpha);
+            hipLaunchKernelGGL(k_axpy_faces, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx, -alpha);
+            HIP_TRY(hipGetLastError());
+            ST_TRY(project(c, c->r));
+            if (precond == STOKES_SIMPLE) {
+                ST_TRY(cg_S(c, c->r, c->eps_S, &itS, &stS));
+                totS += itS;
+                note_inner(stS);
+                ST_TRY(project(c, c->zs));
+            }
+            ST_TRY(dots(c, c->r, z, c->r, c->r, z, z, dd));
+            ++k;
+            rel = std::sqrt(dd[1]) / r0;
+            relz = std::sqrt(dd[2]) / z0;
+            if (!std::isfinite(rel) || !std::isfinite(relz)) {
+                status = STOKES_E_BREAKDOWN;
+                break;
+            }
+            const bool stop = c->stop_prec ? (relz < tol) : (rel < tol);
+            double beta = 0.0;
+            if (!stop) {
+                beta = dd[0] / rz;
+                rz = dd[0];
+                hipLaunchKernelGGL(k_dir_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->d, z, beta);
+                HIP_TRY(hipGetLastError());
+            }
+            alphas.push_back(alpha);
+            if (!stop) betas.push_back(beta);
+            double sums[3], mean[3];
+            ST_TRY(face_sums(c, c->u, sums));
+            const double kk = kvox_of(c, sums, mean) / N2;
+            c->hist.insert(c->hist.end(), {rel, relz, kk, (double)(totA - a0), (double)(totS - s0), alpha, beta, 0.0});
+            if (stop) break;
+        }
+    }
+    ST_TRY(project(c, c->p));
+
+    // optional true velocity u = A^{-1}(f - B^T p) (eq. velocity_schur)
+    if (c->true_velocity && status >= 0) {
+        hipLaunchKernelGGL(k_force_minus_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->p, c->force[0],
+                           c->force[1], c->force[2], c->fr);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(cg_A(c, c->fr, c->eps_A, &itA, &stA));
+        totA += itA;
+        note_inner(stA);
+        std::swap(c->u, c->fx);
+    }
+
+    double sums[3], mean[3];
+    ST_TRY(face_sums(c, c->u, sums));
+    R.k_vox = kvox_of(c, sums, mean);
+    R.k_hat = R.k_vox / N2;
+    for (int a = 0; a < 3; ++a) R.mean_u[a] = mean[a];
+    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->q);
+    HIP_TRY(hipGetLastError());
+    double dv[3];
+    ST_TRY(dots(c, c->q, c->q, nullptr, nullptr, nullptr, nullptr, dv));
+    R.div_norm = std::sqrt(dv[0]);
+    R.outer_iters = k;
+    R.inner_A_iters = (int)totA;
+    R.inner_S_iters = (int)totS;
+    R.rel_res = rel;
+    R.rel_res_prec = relz;
+    if (!alphas.empty()) {
+        lanczos_extremes(alphas, betas, &R.ritz_min, &R.ritz_max);
+        R.cond_est = R.ritz_max / R.ritz_min;
+    }
+    R.status = status;
+    ST_TRY(collect_timing(c));
+    c->have_solution = status >= 0;
+    return (stokes_status)status;
+}
+
+stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, stokes_report* report) {
+    if (!c) return STOKES_E_ARG;
+    if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    stokes_status st;
+    try {
+        st = solve_impl(c, precond, tol);
+    } catch (const std::bad_alloc&) {
+        st = STOKES_E_NOMEM;
+    }
+    c->rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = c->rep;
+    return st;
+}
+
+stokes_status stokes_permeability(stokes_ctx* c, double* k_hat) {
+    if (!c || !k_hat) return STOKES_E_ARG;
+    if (!c->have_solution) return STOKES_E_STATE;
+    *k_hat = c->rep.k_hat;
+    return STOKES_OK;
+}
+
+stokes_status stokes_get_report(stokes_ctx* c, stokes_report* report) {
+    if (!c || !report) return STOKES_E_ARG;
+    if (!c->have_solution) return STOKES_E_STATE;
+    *report = c->rep;
+    return STOKES_OK;
+}
+
+stokes_status stokes_history(stokes_ctx* c, double* out, int cap, int* n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && !out)) return STOKES_E_ARG;
+    const int n = (int)(c->hist.size() / 8);
+    *n_out = n;
+    const int m = std::min(n, cap);
+    if (m > 0) std::memcpy(out, c->hist.data(), (size_t)m * 8 * sizeof(double));
+    return STOKES_OK;
+}
+
+stokes_status stokes_get_fields(stokes_ctx* c, double* p, double* u) {
+    if (!c) return STOKES_E_ARG;
+    if (!c->have_solution) return STOKES_E_STATE;
+    if (p) HIP_TRY(hipMemcpyAsync(p, c->p, (size_t)c->n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (u) HIP_TRY(hipMemcpyAsync(u, c->u, (size_t)(3 * c->n3) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return STOKES_OK;
+}
+
+// Operators on device fields.  The input is first copied into context
+// scratch (inner-solve work vectors; the solution p, u is not touched) and
+// masked, so entries that are not unknowns are ignored.
+static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double* out, hipMemcpyKind kin,
+                                hipMemcpyKind kout) {
+    const Sweep& s = c->sw;
+    const int64_t n3 = c->n3;
+    const bool face_in = op == STOKES_OP_A || op == STOKES_OP_B;
+    const bool face_out = op == STOKES_OP_A || op == STOKES_OP_BT || op == STOKES_OP_DIAG_A;
+    const bool no_in = op == STOKES_OP_DIAG_A || op == STOKES_OP_DIAG_SHAT;
+    double* src = face_in ? c->fd : c->sd;
+    double* dst = face_out ? c->fq : c->sq;
+    if (!no_in) {
+        if (!in) return STOKES_E_ARG;
+        HIP_TRY(hipMemcpyAsync(src, in, (size_t)((face_in ? 3 : 1) * n3) * sizeof(double), kin, c->stream));
+        if (face_in) hipLaunchKernelGGL(k_mask_faces, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src);
+        else hipLaunchKernelGGL(k_mask_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->bits, c->wpr, src);
+    }
+    switch (op) {
+    case STOKES_OP_A: hipLaunchKernelGGL(k_apply_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, dst); break;
+    case STOKES_OP_B: hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, src, dst); break;
+    case STOKES_OP_BT: hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, dst); break;
+    case STOKES_OP_SHAT: hipLaunchKernelGGL(k_apply_Shat, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, dst); break;
+    case STOKES_OP_DIAG_A: hipLaunchKernelGGL(k_diag_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, dst); break;
+    case STOKES_OP_DIAG_SHAT: hipLaunchKernelGGL(k_diag_Shat, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, dst); break;
+    case STOKES_OP_PROJECT:
+        HIP_TRY(hipMemcpyAsync(dst, src, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        ST_TRY(project(c, dst));
+        break;
+    case STOKES_OP_S: {
+        hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, c->fr);
+        int it = 0, st = 0;
+        ST_TRY(cg_A(c, c->fr, c->eps_A, &it, &st));
+        if (st == -4) return STOKES_E_BREAKDOWN;
+        hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx, dst);
+        break;
+    }
+    default: return STOKES_E_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, dst, (size_t)((face_out ? 3 : 1) * n3) * sizeof(double), kout, c->stream));
+    return STOKES_OK;
+}
+
+stokes_status stokes_apply(stokes_ctx* c, int op, const double* in, double* out) {
+    if (!c || !out || op < 0 || op > STOKES_OP_S) return STOKES_E_ARG;
+    ST_TRY(apply_impl(c, op, in, out, hipMemcpyHostToDevice, hipMemcpyDeviceToHost));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return STOKES_OK;
+}
+
+stokes_status stokes_apply_device(stokes_ctx* c, int op, const double* in, double* out) {
+    if (!c || !out || op < 0 || op > STOKES_OP_S) return STOKES_E_ARG;
+    return apply_impl(c, op, in, out, hipMemcpyDeviceToDevice, hipMemcpyDeviceToDevice);
+}
+
+stokes_status stokes_info(stokes_ctx* c, int64_t info[12]) {
+    if (!c || !info) return STOKES_E_ARG;
+    info[0] = c->N;
+    info[1] = c->nfluid_in;
+    info[2] = c->nfluid;
+    info[3] = c->nsurf;
+    info[4] = c->ncomp_all;
+    info[5] = c->ncomp_kept;
+    info[6] = c->nface[0];
+    info[7] = c->nface[1];
+    info[8] = c->nface[2];
+    info[9] = c->device_bytes;
+    info[10] = 0;
+    info[11] = 0;
+    return STOKES_OK;
+}
+
+stokes_status stokes_kernel_timing(stokes_ctx* c, double* ms_total, int64_t* launches, int64_t* cells) {
+    if (!c || !ms_total || !launches || !cells) return STOKES_E_ARG;
+    ST_TRY(collect_timing(c));
+    *ms_total = c->timing_ms;
+    *launches = c->timing_launches;
+    *cells = c->n3;
+    c->timing_ms = 0.0;
+    c->timing_launches = 0;
+    return STOKES_OK;
+}
+
+void stokes_destroy(stokes_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    release(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""Thin ctypes binding of libstokes.so (include/stokes.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+The functions keep the C names; `Stokes` wraps one context.  torch is
+imported before the library is loaded so that the process holds a single HIP
+runtime (torch's), and torch provides the device memory of caller-side
+tensors and the stream the library runs on.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede the library load: one HIP runtime per process)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstokes.so")
+
+STOKES_OK, STOKES_NOT_CONVERGED = 0, 1
+STOKES_E_ARG, STOKES_E_NOMEM, STOKES_E_DEVICE, STOKES_E_BREAKDOWN, STOKES_E_STATE, STOKES_E_LIMIT = \
+    -1, -2, -3, -4, -5, -6
+STOKES_UZAWA, STOKES_SIMPLE = 0, 1
+(STOKES_OP_A, STOKES_OP_B, STOKES_OP_BT, STOKES_OP_SHAT, STOKES_OP_DIAG_A, STOKES_OP_DIAG_SHAT,
+ STOKES_OP_PROJECT, STOKES_OP_S) = range(8)
+STOKES_KEEP_ALL_COMPONENTS = 0x1
+STOKES_FLAG_NO_FLOW, STOKES_FLAG_ZERO_RHS, STOKES_FLAG_INNER_MAXIT = 0x1, 0x2, 0x4
+
+EXPORTED = [
+    "stokes_setup", "stokes_setup_ex", "stokes_set_stream", "stokes_set_option", "stokes_solve",
+    "stokes_permeability", "stokes_get_report", "stokes_history", "stokes_get_fields",
+    "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
+    "stokes_destroy", "stokes_status_str", "stokes_preprocess",
+]
+
+
+class StokesReport(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("flags", ctypes.c_uint),
+        ("outer_iters", ctypes.c_int), ("inner_A_iters", ctypes.c_int), ("inner_S_iters", ctypes.c_int),
+        ("n_components", ctypes.c_int), ("n_components_kept", ctypes.c_int),
+        ("k_hat", ctypes.c_double), ("k_vox", ctypes.c_double), ("mean_u", ctypes.c_double * 3),
+        ("rel_res", ctypes.c_double), ("rel_res_prec", ctypes.c_double), ("r0_norm", ctypes.c_double),
+        ("div_norm", ctypes.c_double), ("cond_est", ctypes.c_double),
+        ("ritz_min", ctypes.c_double), ("ritz_max", ctypes.c_double),
+        ("porosity", ctypes.c_double), ("porosity_effective", ctypes.c_double),
+        ("stv_ratio", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "mean_u" else v
+        return d
+
+
+class StokesError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libstokes.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run paper_2307_05266_amd.build.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "stokes_setup": ([ctypes.POINTER(vp), vp, ip, dp], ip),
+        "stokes_setup_ex": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint], ip),
+        "stokes_set_stream": ([vp, vp], ip),
+        "stokes_set_option": ([vp, ctypes.c_char_p, ctypes.c_double], ip),
+        "stokes_solve": ([vp, ip, ctypes.c_double, ctypes.POINTER(StokesReport)], ip),
+        "stokes_permeability": ([vp, dp], ip),
+        "stokes_get_report": ([vp, ctypes.POINTER(StokesReport)], ip),
+        "stokes_history": ([vp, vp, ip, ctypes.POINTER(ip)], ip),
+        "stokes_get_fields": ([vp, vp, vp], ip),
+        "stokes_apply": ([vp, ip, vp, vp], ip),
+        "stokes_apply_device": ([vp, ip, vp, vp], ip),
+        "stokes_info": ([vp, i64p], ip),
+        "stokes_kernel_timing": ([vp, dp, i64p, i64p], ip),
+        "stokes_destroy": ([vp], None),
+        "stokes_status_str": ([ip], ctypes.c_char_p),
+        "stokes_preprocess": ([vp, ip, dp, ctypes.c_uint, i64p, vp, vp], ip),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().stokes_status_str(int(s)).decode()
+
+
+def _check(st, what, ok=(STOKES_OK,)):
+    if st not in ok:
+        raise StokesError(st, what)
+    return st
+
+
+# ---- functions with the C names ---------------------------------------------------
+def stokes_setup(mask, N, force, flags=0):
+    lib = load()
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    if m.size != N ** 3:
+        raise ValueError("mask must hold N^3 bytes")
+    f = np.ascontiguousarray(force, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = lib.stokes_setup_ex(ctypes.byref(h), m.ctypes.data, int(N),
+                             f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_uint(flags))
+    _check(st, "stokes_setup")
+    return h
+
+
+def stokes_preprocess(mask, N, force, flags=0, want_fields=True):
+    """Host-only geometry preprocessing: counts, kept-fluid mask, component labels."""
+    lib = load()
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    if m.size != N ** 3:
+        raise ValueError("mask must hold N^3 bytes")
+    f = np.ascontiguousarray(force, dtype=np.float64)
+    counts = (ctypes.c_int64 * 6)()
+    fluid = np.zeros(N ** 3, dtype=np.uint8) if want_fields else None
+    label = np.zeros(N ** 3, dtype=np.int32) if want_fields else None
+    st = lib.stokes_preprocess(m.ctypes.data, int(N), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_uint(flags), counts,
+                               fluid.ctypes.data if want_fields else None,
+                               label.ctypes.data if want_fields else None)
+    _check(st, "stokes_preprocess")
+    keys = ["nfluid_in", "nfluid", "nsurf", "ncomp_all", "ncomp_kept"]
+    out = {k: int(counts[i]) for i, k in enumerate(keys)}
+    if want_fields:
+        out["fluid"] = fluid.reshape(N, N, N)
+        out["label"] = label.reshape(N, N, N)
+    return out
+
+
+def stokes_set_stream(ctx, stream):
+    return _check(load().stokes_set_stream(ctx, ctypes.c_void_p(stream)), "stokes_set_stream")
+
+
+def stokes_set_option(ctx, key, value):
+    return _check(load().stokes_set_option(ctx, key.encode(), float(value)), f"stokes_set_option({key})")
+
+
+def stokes_solve(ctx, precond, tol):
+    rep = StokesReport()
+    st = load().stokes_solve(ctx, int(precond), float(tol), ctypes.byref(rep))
+    _check(st, "stokes_solve", ok=(STOKES_OK, STOKES_NOT_CONVERGED))
+    return st, rep.to_dict()
+
+
+def stokes_permeability(ctx):
+    k = ctypes.c_double()
+    _check(load().stokes_permeability(ctx, ctypes.byref(k)), "stokes_permeability")
+    return k.value
+
+
+def stokes_history(ctx, cap=100000):
+    n = ctypes.c_int()
+    out = np.zeros((cap, 8))
+    _check(load().stokes_history(ctx, out.ctypes.data, cap, ctypes.byref(n)), "stokes_history")
+    return out[:min(n.value, cap)].copy()
+
+
+def stokes_get_fields(ctx, N):
+    p = np.zeros(N ** 3)
+    u = np.zeros(3 * N ** 3)
+    _check(load().stokes_get_fields(ctx, p.ctypes.data, u.ctypes.data), "stokes_get_fields")
+    return p.reshape(N, N, N), u.reshape(3, N, N, N)
+
+
+def _op_shapes(op, N):
+    face_in = op in (STOKES_OP_A, STOKES_OP_B)
+    face_out = op in (STOKES_OP_A, STOKES_OP_BT, STOKES_OP_DIAG_A)
+    return (3 * N ** 3 if face_in else N ** 3), (3 * N ** 3 if face_out else N ** 3), face_out
+
+
+def stokes_apply(ctx, op, x, N):
+    nin, nout, face_out = _op_shapes(op, N)
+    if x is None:
+        xin = np.zeros(nin)
+    else:
+        xin = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        if xin.size != nin:
+            raise ValueError("input has the wrong size for this operator")
+    out = np.zeros(nout)
+    _check(load().stokes_apply(ctx, int(op), xin.ctypes.data, out.ctypes.data), "stokes_apply")
+    return out.reshape((3, N, N, N) if face_out else (N, N, N))
+
+
+def stokes_apply_device(ctx, op, x, out):
+    """x, out: contiguous float64 torch tensors on the GPU (sizes as in stokes_apply)."""
+    for t in (x, out):
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError("stokes_apply_device needs contiguous float64 GPU tensors")
+    xp = x.data_ptr() if x is not None else None
+    return _check(load().stokes_apply_device(ctx, int(op), ctypes.c_void_p(xp), ctypes.c_void_p(out.data_ptr())),
+                  "stokes_apply_device")
+
+
+def stokes_info(ctx):
+    info = (ctypes.c_int64 * 12)()
+    _check(load().stokes_info(ctx, info), "stokes_info")
+    keys = ["N", "nfluid_in", "nfluid", "nsurf", "ncomp_all", "ncomp_kept", "nface_x", "nface_y", "nface_z",
+            "device_bytes"]
+    return {k: int(info[i]) for i, k in enumerate(keys)}
+
+
+def stokes_kernel_timing(ctx):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    cells = ctypes.c_int64()
+    _check(load().stokes_kernel_timing(ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cells)),
+           "stokes_kernel_timing")
+    return ms.value, n.value, cells.value
+
+
+def stokes_destroy(ctx):
+    if ctx:
+        load().stokes_destroy(ctx)
+
+
+# ---- convenience wrapper ------------------------------------------------------------
+class Stokes:
+    """One geometry on the GPU.  mask: uint8 (N, N, N) indexed [k][j][i], 1 = fluid."""
+
+    def __init__(self, mask, force=(1.0, 0.0, 0.0), keep_all=False, stream=None, **options):
+        mask = np.asarray(mask)
+        self.N = int(mask.shape[0])
+        self._ctx = stokes_setup(mask, self.N, force, STOKES_KEEP_ALL_COMPONENTS if keep_all else 0)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        if stream is not None:
+            stokes_set_stream(self._ctx, stream)
+        for k, v in options.items():
+            stokes_set_option(self._ctx, k, v)
+
+    def set_option(self, key, value):
+        stokes_set_option(self._ctx, key, value)
+
+    def solve(self, precond=STOKES_SIMPLE, tol=1e-8):
+        if isinstance(precond, str):
+            precond = {"uzawa": STOKES_UZAWA, "simple": STOKES_SIMPLE}[precond.lower()]
+        st, rep = stokes_solve(self._ctx, precond, tol)
+        return rep
+
+    def permeability(self):
+        return stokes_permeability(self._ctx)
+
+    def history(self):
+        return stokes_history(self._ctx)
+
+    def fields(self):
+        return stokes_get_fields(self._ctx, self.N)
+
+    def apply(self, op, x=None):
+        return stokes_apply(self._ctx, op, x, self.N)
+
+    def apply_device(self, op, x, out):
+        return stokes_apply_device(self._ctx, op, x, out)
+
+    def info(self):
+        return stokes_info(self._ctx)
+
+    def kernel_timing(self):
+        return stokes_kernel_timing(self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            stokes_destroy(self._ctx)
+            self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

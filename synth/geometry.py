@@ -102,7 +102,7 @@ def grf(N: int, corr_len: float, target_porosity: float, seed: int,
     kx = 2 * np.pi * np.fft.rfftfreq(N)
     filt = np.exp(-0.5 * s * s * (kz[:, None, None] ** 2 + kz[None, :, None] ** 2
                                   + kx[None, None, :] ** 2))
-    field = np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N)).ravel()
+    field = np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N), axes=(0, 1, 2)).ravel()
     del w
     n_fluid = int(round(target_porosity * field.size))
     order = np.argsort(-field, kind="stable")
