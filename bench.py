@@ -25,9 +25,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per voxel of one A-stencil sweep in FP64: 3 face values read,
-# 3 written (8 B each), 1 face-code byte read
-A_STENCIL_BYTES_PER_CELL = 6 * 8 + 1
 
 
 def log(*a):
@@ -76,6 +73,7 @@ def main():
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--precond", default="simple", choices=["simple", "uzawa"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep-blocks", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this solver has no multi-GPU path",
@@ -85,6 +83,7 @@ def main():
     import torch
 
     import paper_2307_05266_amd as P
+    from paper_2307_05266_amd.stokes import KERNEL_NAMES
     from synth import spheres
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -100,6 +99,8 @@ def main():
     s = P.Stokes(mask, (1.0, 0.0, 0.0), stream=stream.cuda_stream)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
+    if args.sweep_blocks:
+        s.set_option("sweep_blocks", args.sweep_blocks)
     info = s.info()
     log(f"[bench] setup {setup_ms:.1f} ms, fluid {info['nfluid']} components {info['ncomp_kept']}")
 
@@ -108,8 +109,9 @@ def main():
         log(f"[bench] warmup {w}: {rep['seconds']:.3f} s outer={rep['outer_iters']} "
             f"innerA={rep['inner_A_iters']} innerS={rep['inner_S_iters']} k={rep['k_hat']:.10e}")
 
-    s.set_option("kernel_timing", 1)
-    s.kernel_timing()  # reset
+    s.set_option("kernel_timing", 8)   # time every 8th launch of each inner kernel
+    for kind in range(len(KERNEL_NAMES)):
+        s.kernel_timing(kind)  # reset
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -121,12 +123,17 @@ def main():
         log(f"[bench] step {k}: {lat[-1]:.3f} s outer={rep['outer_iters']} k={kh:.12e}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    ms_total, launches, cells = s.kernel_timing()
+    kernels = {}
+    for kind, name in enumerate(KERNEL_NAMES):
+        ms, n, nbytes = s.kernel_timing(kind)
+        if n == 0:
+            continue
+        avg = ms / n
+        kernels[name] = {"ms_total": ms, "launches": n, "avg_launch_us": avg * 1e3,
+                         "bytes_per_launch": nbytes, "GBps": nbytes / (avg * 1e-3) / 1e9}
     s.set_option("kernel_timing", 0)
-
-    avg_launch_ms = ms_total / max(launches, 1)
-    bytes_per_launch = A_STENCIL_BYTES_PER_CELL * cells
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    achieved = kernels[dom]["GBps"]
     lat_sorted = sorted(lat)
 
     def pct(q):
@@ -164,17 +171,18 @@ def main():
         "setup_ms": setup_ms,
         "cell_updates_per_s": (sweeps_A + sweeps_S) * N ** 3 * args.steps / total,
         "roofline": {
-            "kernel": "k_cgA_stencil",
+            "kernel": dom,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "launches": launches,
-            "avg_launch_us": avg_launch_ms * 1e3,
-            "bytes_per_launch": bytes_per_launch,
+            "launches": kernels[dom]["launches"],
+            "avg_launch_us": kernels[dom]["avg_launch_us"],
+            "bytes_per_launch": kernels[dom]["bytes_per_launch"],
         },
+        "kernels": kernels,
     }
     s.close()
     if not args.no_cpu_baseline:

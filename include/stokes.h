@@ -150,8 +150,10 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "stop_prec"   0: stop on ||r||/||r0|| (default); 1: on ||z||/||z0||
  *                 (the preconditioned norm of Algorithm 1)
  *   "check_every" inner iterations queued between convergence checks (default 0 = adaptive)
- *   "kernel_timing" 1: time every launch of the A-stencil kernel with HIP events
+ *   "kernel_timing" n > 0: time every n-th launch of each inner-loop kernel with
+ *                 HIP events (0 = off, the default)
  *   "true_velocity" 1: after the solve, recompute u = A^{-1}(f - B^T p)
+ *   "sweep_blocks" number of workgroups a sweep aims for (default 1024)
  * Unknown keys or out-of-range values give STOKES_E_ARG.
  */
 stokes_status stokes_set_option(stokes_ctx *ctx, const char *key, double value);
@@ -196,11 +198,15 @@ stokes_status stokes_apply_device(stokes_ctx *ctx, int op, const double *in, dou
  * device bytes held, 0, 0. */
 stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
 
-/* Time spent in the A-stencil kernel over the solves since the last call,
- * measured with HIP events on the context's stream when "kernel_timing" is
- * on: total milliseconds, number of launches, and cells swept per launch. */
-stokes_status stokes_kernel_timing(stokes_ctx *ctx, double *ms_total, int64_t *launches,
-                                   int64_t *cells_per_launch);
+/* Device time of the inner-loop kernels since the last call for that kernel,
+ * measured with HIP events around the sampled launches (see "kernel_timing")
+ * on the context's stream.  kernel: 0 = A direction, 1 = A stencil,
+ * 2 = A update, 3 = SIMPLE direction, 4 = SIMPLE stencil, 5 = SIMPLE update.  Returns the total
+ * milliseconds and the number of timed launches (launches queued after
+ * convergence return at once and are counted too), and the algorithmic bytes one launch
+ * moves (each input read once, each output written once, in FP64). */
+stokes_status stokes_kernel_timing(stokes_ctx *ctx, int kernel, double *ms_total, int64_t *launches,
+                                   double *bytes_per_launch);
 
 /* Free everything the context holds.  NULL is ignored. */
 void stokes_destroy(stokes_ctx *ctx);

@@ -21,10 +21,12 @@
 // remapped so each of the 8 XCDs (private L2 each) receives a contiguous
 // range of columns, which keeps y- and z-neighbour rows in one L2.
 //
-// Reductions are deterministic: each block writes one partial per quantity,
-// the last block to arrive (atomic ticket) adds the partials in block order
-// and finishes the scalar recurrences on the device, so inner CG loops run
-// without host round trips.
+// Reductions are deterministic and need neither atomics nor fences: each
+// block writes one partial per quantity with a plain store; the next kernel
+// (after the kernel boundary has made those stores visible) has every block
+// add all partials in block order, so every block derives bit-identical CG
+// scalars on its own and inner loops run without host round trips.  (A
+// device-scope fence per block would write back the XCD's L2 each time.)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,8 +38,10 @@ namespace stokes {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxBlocks = 4096;      // partial slots per reduced quantity
-constexpr int kMaxParts = 4;          // quantities reduced by one kernel
 constexpr int kMaxCompLds = 2048;     // components handled by the projection kernels
+
+// partial slots of the inner CG loops
+constexpr int kRZ = 0, kZZ = 1, kDQ = 2, kNumSlots = 3;
 
 struct Sweep {
     int N;
@@ -45,15 +49,19 @@ struct Sweep {
     int gx, gy, gz;   // blocks along x, y and z
     int lz;           // z-planes per block
     int nblk;         // gx * gy * gz
+    int N2;           // N * N
+    int n3;           // N^3 (< 2^31 for N <= 800)
 };
 
-// Inner CG state, resident in device memory.
+// Inner CG state, resident in device memory.  Scalars are written by block 0
+// only; rho is double-buffered by iteration parity because the other blocks
+// of the kernel that writes rho_j still read rho_{j-1}.
 struct CgState {
-    double rho;       // (r, z)
-    double alpha, beta;
+    double rho[2];    // (r_j, z_j) at [j & 1]
     double z0;        // ||z_0||
+    double alpha, beta;
     double zrel;      // ||z_j|| / ||z_0||
-    double dq;        // (d, q)
+    double dq;        // (d_j, A d_j)
     double eps;
     int it;           // operator applications so far
     int done;         // 1: stop (converged, capped or broken down)
@@ -61,14 +69,18 @@ struct CgState {
     int maxit;
 };
 
-// Reduction scratch shared by the kernels of one context (stream ordered).
-struct Reduce {
-    double* part;       // [kMaxParts][kMaxBlocks]
-    unsigned* ticket;   // arrival counter, returned to 0 by the last block
-    double* out;        // [8] results of host-side dots
-};
-
-__constant__ double kInvDiagA[6] = {0.0, 1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0, 1.0 / 9.0, 1.0 / 10.0};
+// 1 / diag(A) = 1 / (5 + s) on an active face (s = 1..5), 0 on an inactive one.
+// Selects rather than a table: a per-lane table index would turn every use
+// into a dependent memory load.
+__device__ __forceinline__ double inv_diag_A(int s) {
+    double v = 0.0;
+    v = s == 1 ? 1.0 / 6.0 : v;
+    v = s == 2 ? 1.0 / 7.0 : v;
+    v = s == 3 ? 1.0 / 8.0 : v;
+    v = s == 4 ? 1.0 / 9.0 : v;
+    v = s == 5 ? 1.0 / 10.0 : v;
+    return v;
+}
 
 __device__ __forceinline__ int sx_of(int code) { return code % 6; }
 __device__ __forceinline__ int sy_of(int code) { return (code / 6) % 6; }
@@ -79,11 +91,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
     return (b & 7) * (nblk >> 3) + (b >> 3);
 }
 
+// One thread's column: (i, j) and a run of z-planes [k0, k1), with the
+// periodic in-plane neighbour offsets.
 struct Column {
-    int lb;          // logical block id
-    int i, j;        // this thread's column
-    int k0, k1;      // z-run
+    int lb;                  // logical block id
+    int i, j, k0, k1;
     bool valid;
+    int X0;                  // i + N j
+    int oxm, oxp, oym, oyp;  // offsets to the x/y neighbours (wrapped)
 };
 
 __device__ __forceinline__ Column sweep_column(const Sweep& s) {
@@ -98,7 +113,30 @@ __device__ __forceinline__ Column sweep_column(const Sweep& s) {
     c.k0 = bz * s.lz;
     c.k1 = min(s.N, c.k0 + s.lz);
     c.valid = c.i < s.N && c.j < s.N;
+    const int N = s.N;
+    c.X0 = c.i + N * c.j;
+    c.oxm = c.i == 0 ? N - 1 : -1;
+    c.oxp = c.i == N - 1 ? -(N - 1) : 1;
+    c.oym = c.j == 0 ? (N - 1) * N : -N;
+    c.oyp = c.j == N - 1 ? -(N - 1) * N : N;
     return c;
+}
+
+// Seven-point neighbourhood of voxel (i, j, k) as flat indices within one plane.
+struct Nbr {
+    int X, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nbr neighbours(const Sweep& s, const Column& c, int k) {
+    Nbr n;
+    n.X = c.X0 + k * s.N2;
+    n.xm = n.X + c.oxm;
+    n.xp = n.X + c.oxp;
+    n.ym = n.X + c.oym;
+    n.yp = n.X + c.oyp;
+    n.zm = n.X + (k == 0 ? (s.N - 1) * s.N2 : -s.N2);
+    n.zp = n.X + (k == s.N - 1 ? -(s.N - 1) * s.N2 : s.N2);
+    return n;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -106,10 +144,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block sums of NP values; result valid in thread 0.
+// Block sums of NP values; the totals are returned in every thread.
 template <int NP>
-__device__ __forceinline__ void block_sum(double (&v)[NP]) {
-    __shared__ double lds[kMaxParts][kWaves];
+__device__ __forceinline__ void block_sum_all(double (&v)[NP]) {
+    __shared__ double lds[kNumSlots + 1][kWaves];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
@@ -117,58 +155,41 @@ __device__ __forceinline__ void block_sum(double (&v)[NP]) {
         if (lane == 0) lds[n][w] = v[n];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n) {
-            double a = lds[n][0];
-            for (int q = 1; q < kWaves; ++q) a += lds[n][q];
-            v[n] = a;
-        }
-    }
-    __syncthreads();
-}
-
-// Write this block's partials and take a ticket.  Returns true in every
-// thread of the last block to arrive; that block then holds the totals
-// (added in block order) in v[] of thread 0.
-template <int NP>
-__device__ __forceinline__ bool reduce_across_blocks(double (&v)[NP], const Reduce& red, int lb, int nblk) {
-    __shared__ int am_last;
-    block_sum<NP>(v);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n)
-            __hip_atomic_store(&red.part[n * kMaxBlocks + lb], v[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = atomicAdd(red.ticket, 1u);
-        am_last = (prev == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
-    double acc[NP];
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
-        acc[n] = 0.0;
-        // thread t adds partials t, t + 256, ... in order; then the block tree
-        for (int b = threadIdx.x; b < nblk; b += kBlock)
-            acc[n] += __hip_atomic_load(&red.part[n * kMaxBlocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double a = lds[n][0];
+        for (int q = 1; q < kWaves; ++q) a += lds[n][q];
+        v[n] = a;
     }
-    block_sum<NP>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int n = 0; n < NP; ++n) v[n] = acc[n];
-        __hip_atomic_store(red.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+    __syncthreads();
 }
 
-__device__ __forceinline__ int64_t vidx(int N, int i, int j, int k) {
-    return (int64_t)i + (int64_t)N * ((int64_t)j + (int64_t)N * k);
+// Write this block's partials for slots slot0 .. slot0+NP-1.
+template <int NP>
+__device__ __forceinline__ void write_partials(double (&v)[NP], double* part, int slot0, int lb) {
+    block_sum_all<NP>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int n = 0; n < NP; ++n) part[(slot0 + n) * kMaxBlocks + lb] = v[n];
+    }
+}
+
+// Totals of the partials left by the previous kernel, added in block order;
+// identical bits in every block.
+template <int NP>
+__device__ __forceinline__ void read_totals(const double* part, const int (&slots)[NP], int nblk, double (&tot)[NP]) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) a += part[slots[n] * kMaxBlocks + b];
+        tot[n] = a;
+    }
+    block_sum_all<NP>(tot);
 }
 
 // ---------------------------------------------------------------------------
-// Setup: face codes from the remaining-fluid bitmask
+// Setup: face codes from the remaining-fluid bitmask; inverse diagonal of the
+// SIMPLE matrix
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fluid_bit(const uint32_t* bits, int N, int wpr, int i, int j, int k) {
     i = (i + N) % N;
@@ -202,35 +223,33 @@ __global__ void k_face_codes(Sweep s, const uint32_t* __restrict__ bits, int wpr
             }
             sc[a] = 1 + t;
         }
-        code[vidx(N, i, j, k)] = (uint8_t)(sc[0] + 6 * sc[1] + 36 * sc[2]);
+        code[c.X0 + k * s.N2] = (uint8_t)(sc[0] + 6 * sc[1] + 36 * sc[2]);
+    }
+}
+
+// diag(B diag(A)^-1 B^T) at a voxel: sum over its six faces of 1 / diag(A)_F
+__device__ __forceinline__ double diag_Shat_cell(const uint8_t* __restrict__ code, const Nbr& n, int cdX) {
+    return ((inv_diag_A(sx_of(cdX)) + inv_diag_A(sx_of(code[n.xp]))) +
+            (inv_diag_A(sy_of(cdX)) + inv_diag_A(sy_of(code[n.yp])))) +
+           (inv_diag_A(sz_of(cdX)) + inv_diag_A(sz_of(code[n.zp])));
+}
+
+__global__ void k_inv_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ inv) {
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const Nbr n = neighbours(s, c, k);
+        const double dS = diag_Shat_cell(code, n, code[n.X]);
+        inv[n.X] = dS > 0.0 ? 1.0 / dS : 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Plain operators (no reductions)
 // ---------------------------------------------------------------------------
-struct Nbr {
-    int64_t X, xm, xp, ym, yp, zm, zp;
-};
-
-__device__ __forceinline__ Nbr neighbours(int N, int i, int j, int k) {
-    Nbr n;
-    const int im = i == 0 ? N - 1 : i - 1, ip = i == N - 1 ? 0 : i + 1;
-    const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-    const int km = k == 0 ? N - 1 : k - 1, kp = k == N - 1 ? 0 : k + 1;
-    n.X = vidx(N, i, j, k);
-    n.xm = vidx(N, im, j, k);
-    n.xp = vidx(N, ip, j, k);
-    n.ym = vidx(N, i, jm, k);
-    n.yp = vidx(N, i, jp, k);
-    n.zm = vidx(N, i, j, km);
-    n.zp = vidx(N, i, j, kp);
-    return n;
-}
-
 // (A u)_F = (5 + s_F) u_F - sum of the six neighbour faces of the same plane
 __device__ __forceinline__ double apply_A_face(const double* __restrict__ u, const Nbr& n, int s) {
-    const double nb = u[n.xm] + u[n.xp] + u[n.ym] + u[n.yp] + u[n.zm] + u[n.zp];
+    const double nb = ((u[n.xm] + u[n.xp]) + (u[n.ym] + u[n.yp])) + (u[n.zm] + u[n.zp]);
     return (double)(5 + s) * u[n.X] - nb;
 }
 
@@ -238,14 +257,13 @@ __global__ void k_apply_A(Sweep s, const uint8_t* __restrict__ code, const doubl
                           double* __restrict__ out) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
+        const Nbr n = neighbours(s, c, k);
         const int cd = code[n.X];
         const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            out[a * n3 + n.X] = sc[a] ? apply_A_face(u + a * n3, n, sc[a]) : 0.0;
+            out[(size_t)a * s.n3 + n.X] = sc[a] ? apply_A_face(u + (size_t)a * s.n3, n, sc[a]) : 0.0;
     }
 }
 
@@ -254,67 +272,60 @@ __global__ void k_apply_BT(Sweep s, const uint8_t* __restrict__ code, const doub
                            double* __restrict__ out) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
+    double* ox = out;
+    double* oy = out + (size_t)s.n3;
+    double* oz = out + 2 * (size_t)s.n3;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
+        const Nbr n = neighbours(s, c, k);
         const int cd = code[n.X];
         const double pX = p[n.X];
-        out[n.X] = sx_of(cd) ? pX - p[n.xm] : 0.0;
-        out[n3 + n.X] = sy_of(cd) ? pX - p[n.ym] : 0.0;
-        out[2 * n3 + n.X] = sz_of(cd) ? pX - p[n.zm] : 0.0;
+        ox[n.X] = sx_of(cd) ? pX - p[n.xm] : 0.0;
+        oy[n.X] = sy_of(cd) ? pX - p[n.ym] : 0.0;
+        oz[n.X] = sz_of(cd) ? pX - p[n.zm] : 0.0;
     }
 }
 
-// (B u)_X = sum_c [u(c, X) - u(c, X + e_c)]  (0 in solid cells by the invariant)
 // f - B^T p on active faces (right-hand side of the velocity recovery)
 __global__ void k_force_minus_BT(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p, double f0,
                                  double f1, double f2, double* __restrict__ out) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
+    double* ox = out;
+    double* oy = out + (size_t)s.n3;
+    double* oz = out + 2 * (size_t)s.n3;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
+        const Nbr n = neighbours(s, c, k);
         const int cd = code[n.X];
         const double pX = p[n.X];
-        out[n.X] = sx_of(cd) ? f0 - (pX - p[n.xm]) : 0.0;
-        out[n3 + n.X] = sy_of(cd) ? f1 - (pX - p[n.ym]) : 0.0;
-        out[2 * n3 + n.X] = sz_of(cd) ? f2 - (pX - p[n.zm]) : 0.0;
+        ox[n.X] = sx_of(cd) ? f0 - (pX - p[n.xm]) : 0.0;
+        oy[n.X] = sy_of(cd) ? f1 - (pX - p[n.ym]) : 0.0;
+        oz[n.X] = sz_of(cd) ? f2 - (pX - p[n.zm]) : 0.0;
     }
 }
 
+// (B u)_X = sum_c [u(c, X) - u(c, X + e_c)]  (0 in solid cells by the invariant)
 __global__ void k_apply_B(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
+    const double* ux = u;
+    const double* uy = u + (size_t)s.n3;
+    const double* uz = u + 2 * (size_t)s.n3;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
-        out[n.X] = (u[n.X] - u[n.xp]) + (u[n3 + n.X] - u[n3 + n.yp]) + (u[2 * n3 + n.X] - u[2 * n3 + n.zp]);
+        const Nbr n = neighbours(s, c, k);
+        out[n.X] = ((ux[n.X] - ux[n.xp]) + (uy[n.X] - uy[n.yp])) + (uz[n.X] - uz[n.zp]);
     }
 }
 
 // SIMPLE matrix: (Shat p)_X = sum over active faces F of X of (p_X - p_nbr) / diag(A)_F
-__device__ __forceinline__ double apply_Shat_cell(const double* __restrict__ p, const uint8_t* __restrict__ code,
-                                                  const Nbr& n, int cdX, double* diag_out) {
-    const double pX = p[n.X];
-    const int sxl = sx_of(cdX), syl = sy_of(cdX), szl = sz_of(cdX);
-    const int sxh = sx_of(code[n.xp]), syh = sy_of(code[n.yp]), szh = sz_of(code[n.zp]);
-    const double wxl = kInvDiagA[sxl], wyl = kInvDiagA[syl], wzl = kInvDiagA[szl];
-    const double wxh = kInvDiagA[sxh], wyh = kInvDiagA[syh], wzh = kInvDiagA[szh];
-    double acc = 0.0;
-    acc += wxl * (pX - p[n.xm]);
-    acc += wxh * (pX - p[n.xp]);
-    acc += wyl * (pX - p[n.ym]);
-    acc += wyh * (pX - p[n.yp]);
-    acc += wzl * (pX - p[n.zm]);
-    acc += wzh * (pX - p[n.zp]);
-    if (diag_out) *diag_out = ((wxl + wxh) + (wyl + wyh)) + (wzl + wzh);
-    return acc;
-}
-
-__device__ __forceinline__ double diag_Shat_cell(const uint8_t* __restrict__ code, const Nbr& n, int cdX) {
-    return ((kInvDiagA[sx_of(cdX)] + kInvDiagA[sx_of(code[n.xp])]) +
-            (kInvDiagA[sy_of(cdX)] + kInvDiagA[sy_of(code[n.yp])])) +
-           (kInvDiagA[sz_of(cdX)] + kInvDiagA[sz_of(code[n.zp])]);
+__device__ __forceinline__ double apply_Shat_cell(const double pX, const double pxm, const double pxp,
+                                                  const double pym, const double pyp, const double pzm,
+                                                  const double pzp, const uint8_t* __restrict__ code, const Nbr& n,
+                                                  int cdX) {
+    const double wxl = inv_diag_A(sx_of(cdX)), wyl = inv_diag_A(sy_of(cdX)), wzl = inv_diag_A(sz_of(cdX));
+    const double wxh = inv_diag_A(sx_of(code[n.xp])), wyh = inv_diag_A(sy_of(code[n.yp])),
+                 wzh = inv_diag_A(sz_of(code[n.zp]));
+    return ((wxl * (pX - pxm) + wxh * (pX - pxp)) + (wyl * (pX - pym) + wyh * (pX - pyp))) +
+           (wzl * (pX - pzm) + wzh * (pX - pzp));
 }
 
 __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p,
@@ -322,20 +333,19 @@ __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const do
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
-        out[n.X] = apply_Shat_cell(p, code, n, code[n.X], nullptr);
+        const Nbr n = neighbours(s, c, k);
+        out[n.X] = apply_Shat_cell(p[n.X], p[n.xm], p[n.xp], p[n.ym], p[n.yp], p[n.zm], p[n.zp], code, n, code[n.X]);
     }
 }
 
 __global__ void k_diag_A(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ out) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
+        const int X = c.X0 + k * s.N2;
         const int cd = code[X];
         const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
-        for (int a = 0; a < 3; ++a) out[a * n3 + X] = sc[a] ? (double)(5 + sc[a]) : 0.0;
+        for (int a = 0; a < 3; ++a) out[(size_t)a * s.n3 + X] = sc[a] ? (double)(5 + sc[a]) : 0.0;
     }
 }
 
@@ -343,7 +353,7 @@ __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* _
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
+        const Nbr n = neighbours(s, c, k);
         out[n.X] = diag_Shat_cell(code, n, code[n.X]);
     }
 }
@@ -352,13 +362,12 @@ __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* _
 __global__ void k_mask_faces(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ u) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
+        const int X = c.X0 + k * s.N2;
         const int cd = code[X];
         if (!sx_of(cd)) u[X] = 0.0;
-        if (!sy_of(cd)) u[n3 + X] = 0.0;
-        if (!sz_of(cd)) u[2 * n3 + X] = 0.0;
+        if (!sy_of(cd)) u[(size_t)s.n3 + X] = 0.0;
+        if (!sz_of(cd)) u[2 * (size_t)s.n3 + X] = 0.0;
     }
 }
 
@@ -366,299 +375,316 @@ __global__ void k_mask_cells(Sweep s, const uint32_t* __restrict__ bits, int wpr
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
-        if (!fluid_bit(bits, s.N, wpr, c.i, c.j, k)) p[vidx(s.N, c.i, c.j, k)] = 0.0;
+        if (!fluid_bit(bits, s.N, wpr, c.i, c.j, k)) p[c.X0 + k * s.N2] = 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Inner CG with A (faces), Jacobi preconditioner diag(A) = 5 + s
+// Inner Jacobi-PCG (Saad, Alg. 9.1) in three kernels per iteration j:
+//   dir     : beta_j = rho_j / rho_{j-1} from the update's partials, the
+//             convergence test ||z_j|| / ||z_0|| < eps, d_j = z_j + beta_j d_{j-1}
+//             (pointwise, z = D^-1 r recomputed)
+//   stencil : q = M d_j, partial (d_j, q)
+//   update  : alpha_j = rho_j / (d_j, q); x += alpha d, r -= alpha q,
+//             z = D^-1 r; partials (r, z), (z, z)
+// A separate pointwise direction pass costs one more vector pass than
+// recomputing the direction at the six neighbours inside the stencil, but
+// keeps the stencil at one input array (measured faster on gfx950).
 // ---------------------------------------------------------------------------
-// x = 0, r = b (b == nullptr: the uniform force on active faces), z = D^-1 r,
-// d = z; rho = (r, z), z0 = ||z||.
+// Returns true when this iteration should not run; block 0 records why.
+// first: j == 0, then d_0 = z_0 and z0 = ||z_0|| is recorded.
+__device__ __forceinline__ bool cg_dir_scalars(CgState* st, const double* part, int nblk, int j, double* beta_out) {
+    const int slots[2] = {kRZ, kZZ};
+    double tot[2];
+    read_totals<2>(part, slots, nblk, tot);
+    const double rho = tot[0];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        if (lead) { st->status = -4; st->done = 1; st->it = j; }
+        return true;
+    }
+    const double zn = sqrt(tot[1]);
+    double beta = 0.0, zrel = 1.0;
+    if (j == 0) {
+        if (lead) { st->z0 = zn; st->zrel = 1.0; }
+        if (!(zn > 0.0)) {
+            if (lead) { st->done = 1; st->it = 0; }
+            return true;
+        }
+    } else {
+        zrel = zn / st->z0;
+        if (zrel < st->eps || j >= st->maxit) {
+            if (lead) {
+                st->zrel = zrel;
+                st->it = j;
+                if (!(zrel < st->eps)) st->status = 1;
+                st->done = 1;
+            }
+            return true;
+        }
+        beta = rho / st->rho[(j - 1) & 1];
+    }
+    if (lead) {
+        st->rho[j & 1] = rho;
+        st->beta = beta;
+        st->zrel = zrel;
+    }
+    *beta_out = beta;
+    return false;
+}
+
+__device__ __forceinline__ bool cg_update_scalars(CgState* st, const double* part, int nblk, int j,
+                                                  double* alpha_out) {
+    const int slots[1] = {kDQ};
+    double tot[1];
+    read_totals<1>(part, slots, nblk, tot);
+    const double dq = tot[0];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(dq > 0.0) || !isfinite(dq)) {
+        if (lead) { st->dq = dq; st->status = -4; st->done = 1; st->it = j; }
+        return true;
+    }
+    const double alpha = st->rho[j & 1] / dq;
+    if (lead) {
+        st->dq = dq;
+        st->alpha = alpha;
+        st->it = j + 1;
+    }
+    *alpha_out = alpha;
+    return false;
+}
+
+// ---- A (faces), Jacobi diag(A) = 5 + s -------------------------------------
+// x = 0, r = b (b == nullptr: the uniform force on active faces); partials of
+// (r, z), (z, z) with z = D^-1 r.
 __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const double* b, double f0, double f1,
-                           double f2, double* __restrict__ x, double* r, double* __restrict__ d, CgState* st,
-                           Reduce red, double eps, int maxit) {
+                           double f2, double* __restrict__ x, double* r, CgState* st, double* part, double eps,
+                           int maxit) {
     const Column c = sweep_column(s);
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         const double fc[3] = {f0, f1, f2};
         for (int k = c.k0; k < c.k1; ++k) {
-            const int64_t X = vidx(s.N, c.i, c.j, k);
+            const int X = c.X0 + k * s.N2;
             const int cd = code[X];
             const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int64_t F = a * n3 + X;
+                const size_t F = (size_t)a * s.n3 + X;
                 const double bv = sc[a] ? (b ? b[F] : fc[a]) : 0.0;
-                const double z = bv * kInvDiagA[sc[a]];
+                const double z = bv * inv_diag_A(sc[a]);
                 x[F] = 0.0;
                 r[F] = bv;
-                d[F] = z;
                 acc[0] += bv * z;
                 acc[1] += z * z;
             }
         }
     }
-    if (reduce_across_blocks<2>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->rho = acc[0];
-        st->z0 = sqrt(acc[1]);
-        st->zrel = 1.0;
-        st->alpha = st->beta = st->dq = 0.0;
+    write_partials<2>(acc, part, kRZ, c.lb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->eps = eps;
         st->maxit = maxit;
         st->it = 0;
         st->status = 0;
-        st->done = !(st->z0 > 0.0);
-        if (!isfinite(acc[0]) || !isfinite(acc[1])) { st->status = -4; st->done = 1; }
+        st->done = 0;
+        st->alpha = st->beta = st->dq = 0.0;
     }
 }
 
-// q = A d and (d, q); the last block sets alpha = rho / (d, q)
+// plane a's face state from a voxel's code
+__device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(code) : (a == 1 ? sy_of(code) : sz_of(code)); }
+
+__global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ r,
+                          double* __restrict__ d, CgState* st, double* part, int j) {
+    if (st->done) return;
+    double beta;
+    if (cg_dir_scalars(st, part, s.nblk, j, &beta)) return;
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    const bool first = j == 0;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        const int cd = code[X];
+        const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const size_t F = (size_t)a * s.n3 + X;
+            const double z = r[F] * inv_diag_A(sc[a]);
+            d[F] = first ? z : z + beta * d[F];
+        }
+    }
+}
+
+// q = A d on the faces and the partial (d, q)
 __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ d,
-                              double* __restrict__ q, CgState* st, Reduce red) {
+                              double* __restrict__ q, CgState* st, double* part) {
     if (st->done) return;
     const Column c = sweep_column(s);
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     double acc[1] = {0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s.N, c.i, c.j, k);
+            const Nbr n = neighbours(s, c, k);
             const int cd = code[n.X];
             const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double* da = d + a * n3;
+                const double* __restrict__ da = d + (size_t)a * s.n3;
                 const double v = sc[a] ? apply_A_face(da, n, sc[a]) : 0.0;
-                q[a * n3 + n.X] = v;
+                q[(size_t)a * s.n3 + n.X] = v;
                 acc[0] += da[n.X] * v;
             }
         }
     }
-    if (reduce_across_blocks<1>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->dq = acc[0];
-        if (!(acc[0] > 0.0) || !isfinite(acc[0])) {
-            st->status = -4;
-            st->done = 1;
-        } else {
-            st->alpha = st->rho / acc[0];
-        }
-    }
+    write_partials<1>(acc, part, kDQ, c.lb);
 }
 
-// x += alpha d, r -= alpha q, z = D^-1 r; (r, z), ||z||; the last block tests
-// ||z|| / ||z0|| < eps and otherwise forms beta = (r, z)_new / (r, z)_old
 __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ x,
                              double* __restrict__ r, const double* __restrict__ d, const double* __restrict__ q,
-                             CgState* st, Reduce red) {
+                             CgState* st, double* part, int j) {
     if (st->done) return;
+    double alpha;
+    if (cg_update_scalars(st, part, s.nblk, j, &alpha)) return;
     const Column c = sweep_column(s);
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
-    const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const int64_t X = vidx(s.N, c.i, c.j, k);
+            const int X = c.X0 + k * s.N2;
             const int cd = code[X];
             const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int64_t F = a * n3 + X;
+                const size_t F = (size_t)a * s.n3 + X;
                 x[F] += alpha * d[F];
                 const double rn = r[F] - alpha * q[F];
                 r[F] = rn;
-                const double z = rn * kInvDiagA[sc[a]];
+                const double z = rn * inv_diag_A(sc[a]);
                 acc[0] += rn * z;
                 acc[1] += z * z;
             }
         }
     }
-    if (reduce_across_blocks<2>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->it += 1;
-        st->zrel = sqrt(acc[1]) / st->z0;
-        if (!isfinite(acc[0]) || !isfinite(acc[1])) {
-            st->status = -4;
-            st->done = 1;
-        } else if (st->zrel < st->eps) {
-            st->done = 1;
-        } else if (st->it >= st->maxit) {
-            st->status = 1;
-            st->done = 1;
-        } else {
-            st->beta = acc[0] / st->rho;
-            st->rho = acc[0];
-        }
-    }
+    write_partials<2>(acc, part, kRZ, c.lb);
 }
 
-// d = D^-1 r + beta d
-__global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ r,
-                          double* __restrict__ d, const CgState* st) {
-    if (st->done) return;
-    const Column c = sweep_column(s);
-    if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
-    const double beta = st->beta;
-    for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
-        const int cd = code[X];
-        const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int64_t F = a * n3 + X;
-            d[F] = r[F] * kInvDiagA[sc[a]] + beta * d[F];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Inner CG with the SIMPLE matrix (cells), Jacobi preconditioner diag(Shat)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double inv_or_zero(double v) { return v > 0.0 ? 1.0 / v : 0.0; }
-
-__global__ void k_cgS_init(Sweep s, const uint8_t* __restrict__ code, const double* b, double* __restrict__ x,
-                           double* r, double* __restrict__ d, CgState* st, Reduce red, double eps, int maxit) {
+// ---- SIMPLE matrix (cells), Jacobi with the precomputed inverse diagonal ----
+__global__ void k_cgS_init(Sweep s, const double* __restrict__ invd, const double* b, double* __restrict__ x,
+                           double* r, CgState* st, double* part, double eps, int maxit) {
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s.N, c.i, c.j, k);
-            const double bv = b[n.X];
-            const double z = bv * inv_or_zero(diag_Shat_cell(code, n, code[n.X]));
-            x[n.X] = 0.0;
-            r[n.X] = bv;
-            d[n.X] = z;
+            const int X = c.X0 + k * s.N2;
+            const double bv = b[X];
+            const double z = bv * invd[X];
+            x[X] = 0.0;
+            r[X] = bv;
             acc[0] += bv * z;
             acc[1] += z * z;
         }
     }
-    if (reduce_across_blocks<2>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->rho = acc[0];
-        st->z0 = sqrt(acc[1]);
-        st->zrel = 1.0;
-        st->alpha = st->beta = st->dq = 0.0;
+    write_partials<2>(acc, part, kRZ, c.lb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->eps = eps;
         st->maxit = maxit;
         st->it = 0;
         st->status = 0;
-        st->done = !(st->z0 > 0.0);
-        if (!isfinite(acc[0]) || !isfinite(acc[1])) { st->status = -4; st->done = 1; }
+        st->done = 0;
+        st->alpha = st->beta = st->dq = 0.0;
     }
 }
 
+__global__ void k_cgS_dir(Sweep s, const double* __restrict__ invd, const double* __restrict__ r,
+                          double* __restrict__ d, CgState* st, double* part, int j) {
+    if (st->done) return;
+    double beta;
+    if (cg_dir_scalars(st, part, s.nblk, j, &beta)) return;
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    const bool first = j == 0;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        const double z = r[X] * invd[X];
+        d[X] = first ? z : z + beta * d[X];
+    }
+}
+
+// q = Shat d on the cells and the partial (d, q)
 __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ d,
-                              double* __restrict__ q, CgState* st, Reduce red) {
+                              double* __restrict__ q, CgState* st, double* part) {
     if (st->done) return;
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s.N, c.i, c.j, k);
-            const double v = apply_Shat_cell(d, code, n, code[n.X], nullptr);
+            const Nbr n = neighbours(s, c, k);
+            const double dX = d[n.X];
+            const double v =
+                apply_Shat_cell(dX, d[n.xm], d[n.xp], d[n.ym], d[n.yp], d[n.zm], d[n.zp], code, n, code[n.X]);
             q[n.X] = v;
-            acc[0] += d[n.X] * v;
+            acc[0] += dX * v;
         }
     }
-    if (reduce_across_blocks<1>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->dq = acc[0];
-        if (!(acc[0] > 0.0) || !isfinite(acc[0])) {
-            st->status = -4;
-            st->done = 1;
-        } else {
-            st->alpha = st->rho / acc[0];
-        }
-    }
+    write_partials<1>(acc, part, kDQ, c.lb);
 }
 
-__global__ void k_cgS_update(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ x,
-                             double* __restrict__ r, const double* __restrict__ d, const double* __restrict__ q,
-                             CgState* st, Reduce red) {
+__global__ void k_cgS_update(Sweep s, const double* __restrict__ invd, double* __restrict__ x, double* __restrict__ r,
+                             const double* __restrict__ d, const double* __restrict__ q, CgState* st, double* part,
+                             int j) {
     if (st->done) return;
+    double alpha;
+    if (cg_update_scalars(st, part, s.nblk, j, &alpha)) return;
     const Column c = sweep_column(s);
-    const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s.N, c.i, c.j, k);
-            x[n.X] += alpha * d[n.X];
-            const double rn = r[n.X] - alpha * q[n.X];
-            r[n.X] = rn;
-            const double z = rn * inv_or_zero(diag_Shat_cell(code, n, code[n.X]));
+            const int X = c.X0 + k * s.N2;
+            x[X] += alpha * d[X];
+            const double rn = r[X] - alpha * q[X];
+            r[X] = rn;
+            const double z = rn * invd[X];
             acc[0] += rn * z;
             acc[1] += z * z;
         }
     }
-    if (reduce_across_blocks<2>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        st->it += 1;
-        st->zrel = sqrt(acc[1]) / st->z0;
-        if (!isfinite(acc[0]) || !isfinite(acc[1])) {
-            st->status = -4;
-            st->done = 1;
-        } else if (st->zrel < st->eps) {
-            st->done = 1;
-        } else if (st->it >= st->maxit) {
-            st->status = 1;
-            st->done = 1;
-        } else {
-            st->beta = acc[0] / st->rho;
-            st->rho = acc[0];
-        }
-    }
-}
-
-__global__ void k_cgS_dir(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ r,
-                          double* __restrict__ d, const CgState* st) {
-    if (st->done) return;
-    const Column c = sweep_column(s);
-    if (!c.valid) return;
-    const double beta = st->beta;
-    for (int k = c.k0; k < c.k1; ++k) {
-        const Nbr n = neighbours(s.N, c.i, c.j, k);
-        d[n.X] = r[n.X] * inv_or_zero(diag_Shat_cell(code, n, code[n.X])) + beta * d[n.X];
-    }
+    write_partials<2>(acc, part, kRZ, c.lb);
 }
 
 // ---------------------------------------------------------------------------
 // Outer-loop vector work (scalars from the host)
 // ---------------------------------------------------------------------------
-// up to three dot products of cell vectors, totals to red.out[0..2]
+// up to three dot products of cell vectors; per-block partials to out[3*b + q]
 __global__ void k_dots(Sweep s, const double* a0, const double* b0, const double* a1, const double* b1,
-                       const double* a2, const double* b2, Reduce red) {
+                       const double* a2, const double* b2, double* __restrict__ out) {
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const int64_t X = vidx(s.N, c.i, c.j, k);
+            const int X = c.X0 + k * s.N2;
             acc[0] += a0[X] * b0[X];
             if (a1) acc[1] += a1[X] * b1[X];
             if (a2) acc[2] += a2[X] * b2[X];
         }
     }
-    if (reduce_across_blocks<3>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        red.out[0] = acc[0];
-        red.out[1] = acc[1];
-        red.out[2] = acc[2];
-    }
+    block_sum_all<3>(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[3 * c.lb + q] = acc[q];
 }
 
-// sums of the three velocity planes, totals to red.out[0..2]
-__global__ void k_face_sums(Sweep s, const double* __restrict__ u, Reduce red) {
+// sums of the three velocity planes; per-block partials to out[3*b + c]
+__global__ void k_face_sums(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
     const Column c = sweep_column(s);
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     double acc[3] = {0.0, 0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
-            const int64_t X = vidx(s.N, c.i, c.j, k);
+            const int X = c.X0 + k * s.N2;
             acc[0] += u[X];
-            acc[1] += u[n3 + X];
-            acc[2] += u[2 * n3 + X];
+            acc[1] += u[(size_t)s.n3 + X];
+            acc[2] += u[2 * (size_t)s.n3 + X];
         }
     }
-    if (reduce_across_blocks<3>(acc, red, c.lb, s.nblk) && threadIdx.x == 0) {
-        red.out[0] = acc[0];
-        red.out[1] = acc[1];
-        red.out[2] = acc[2];
-    }
+    block_sum_all<3>(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[3 * c.lb + q] = acc[q];
 }
 
 // p += alpha d, r -= alpha q
@@ -667,7 +693,7 @@ __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restri
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
+        const int X = c.X0 + k * s.N2;
         p[X] += alpha * d[X];
         r[X] -= alpha * q[X];
     }
@@ -677,12 +703,11 @@ __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restri
 __global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __restrict__ v, double a) {
     const Column c = sweep_column(s);
     if (!c.valid) return;
-    const int64_t n3 = (int64_t)s.N * s.N * s.N;
     for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
+        const int X = c.X0 + k * s.N2;
         u[X] += a * v[X];
-        u[n3 + X] += a * v[n3 + X];
-        u[2 * n3 + X] += a * v[2 * n3 + X];
+        u[(size_t)s.n3 + X] += a * v[(size_t)s.n3 + X];
+        u[2 * (size_t)s.n3 + X] += a * v[2 * (size_t)s.n3 + X];
     }
 }
 
@@ -691,7 +716,7 @@ __global__ void k_dir_cells(Sweep s, double* __restrict__ d, const double* __res
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
-        const int64_t X = vidx(s.N, c.i, c.j, k);
+        const int X = c.X0 + k * s.N2;
         d[X] = z[X] + beta * d[X];
     }
 }

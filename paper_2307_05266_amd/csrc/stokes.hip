@@ -41,9 +41,16 @@ namespace {
 constexpr int kMaxN = 800;
 constexpr int kCompBlocks = 256;
 
-struct HostState {
-    CgState s;
-};
+// kinds of timed kernels and their algorithmic bytes per voxel (FP64)
+enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeSStencil = 4, kTimeSUpdate = 5,
+       kTimeKinds = 6 };
+// A dir     : r, d read (3 planes each), code byte read; d written
+// A stencil : d read, code byte read; q written
+// A update  : x, d, r, q read, code byte read; x, r written
+// S dir     : r, inverse diagonal, d read; d written
+// S stencil : d read, code byte read; q written
+// S update  : inverse diagonal, x, d, r, q read; x, r written
+constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1, 6 * 8 + 1, 18 * 8 + 1, 4 * 8, 2 * 8 + 1, 7 * 8};
 
 }  // namespace
 
@@ -69,21 +76,26 @@ struct stokes_ctx {
     double* comp_count = nullptr;  // [K]
     double* comp_part = nullptr;   // [kCompBlocks][K]
     double* comp_mean = nullptr;   // [K]
-    double *fx = nullptr, *fr = nullptr, *fd = nullptr, *fq = nullptr, *u = nullptr;   // faces
-    double *p = nullptr, *r = nullptr, *zs = nullptr, *d = nullptr, *q = nullptr;     // cells
-    double *sr = nullptr, *sd = nullptr, *sq = nullptr;                               // cells (SIMPLE solve)
+    double *fx = nullptr, *fr = nullptr, *fq = nullptr, *u = nullptr;  // faces
+    double* fd = nullptr;                                               // faces, inner direction
+    double *p = nullptr, *r = nullptr, *zs = nullptr, *d = nullptr, *q = nullptr;  // cells
+    double *sr = nullptr, *sq = nullptr, *invdS = nullptr;                         // cells (SIMPLE solve)
+    double* sd = nullptr;                                                          // cells, inner direction
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
-    Reduce red{};
+    double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
+    double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
     std::vector<void*> allocations;
     int64_t device_bytes = 0;
     CgState* host_state = nullptr; // pinned
-    double* host_out = nullptr;    // pinned [8]
+    double* host_part = nullptr;   // pinned [3 * kMaxBlocks]
+    int sweep_blocks = 1024;
 
     // options
     double eps_A = 1e-12, eps_S = 1e-12;
     int max_outer = 5000, max_inner = 100000;
     int stop_prec = 0, check_every = 0, true_velocity = 0;
-    bool timing = false;
+    int timing = 0;                // 0: off; n: time every n-th launch of each inner-loop kernel
+    int64_t timing_seen[6] = {0, 0, 0, 0, 0, 0};
 
     // adaptive polling
     int last_it[2] = {0, 0};
@@ -93,24 +105,29 @@ struct stokes_ctx {
     stokes_report rep{};
     std::vector<double> hist;
 
-    // kernel timing
+    // kernel timing: event pairs around the inner-loop kernels, by kind
     std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
     size_t ev_used = 0;
-    double timing_ms = 0.0;
-    int64_t timing_launches = 0;
+    double timing_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t timing_launches[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
 
-Sweep make_sweep(int N) {
+Sweep make_sweep(int N, int target_blocks) {
     Sweep s{};
     s.N = N;
-    s.bxlog = N >= 64 ? 6 : 5;
+    s.N2 = N * N;
+    s.n3 = N * N * N;
+    // x-extent of a column: 64 unless 32 wastes fewer idle lanes at the row end
+    const int waste64 = (N + 63) / 64 * 64 - N, waste32 = (N + 31) / 32 * 32 - N;
+    s.bxlog = (N >= 64 && waste64 <= waste32) ? 6 : 5;
     const int bx = 1 << s.bxlog, by = kBlock >> s.bxlog;
     s.gx = (N + bx - 1) / bx;
     s.gy = (N + by - 1) / by;
     const int cols = s.gx * s.gy;
-    int gz = std::max(1, std::min(N, (2048 + cols - 1) / cols));
+    int gz = std::max(1, std::min(N, (target_blocks + cols - 1) / cols));
     s.lz = (N + gz - 1) / gz;
     s.gz = (N + s.lz - 1) / s.lz;
     s.nblk = s.gx * s.gy * s.gz;
@@ -134,42 +151,48 @@ void release(stokes_ctx* c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     if (c->host_state) (void)hipHostFree(c->host_state);
-    if (c->host_out) (void)hipHostFree(c->host_out);
+    if (c->host_part) (void)hipHostFree(c->host_part);
     c->host_state = nullptr;
-    c->host_out = nullptr;
+    c->host_part = nullptr;
 }
 
 dim3 grid_of(const Sweep& s) { return dim3((unsigned)s.nblk); }
 
 // ---- inner solves -----------------------------------------------------------
-stokes_status time_begin(stokes_ctx* c) {
-    if (!c->timing) return STOKES_OK;
+// Only every `timing`-th launch of a kind is bracketed, so the events barely
+// perturb the run they measure; the open flag tells time_end whether to close.
+stokes_status time_begin(stokes_ctx* c, int kind, bool* open) {
+    *open = false;
+    if (!c->timing || (c->timing_seen[kind]++ % c->timing) != 0) return STOKES_OK;
+    *open = true;
     if (c->ev_used + 2 > c->ev.size()) {
-        for (int q = 0; q < 256; ++q) {
+        for (int q = 0; q < 512; ++q) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             c->ev.push_back(e);
+            c->ev_kind.push_back(0);
         }
     }
+    c->ev_kind[c->ev_used] = kind;
     HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
     return STOKES_OK;
 }
 
-stokes_status time_end(stokes_ctx* c) {
-    if (!c->timing) return STOKES_OK;
+stokes_status time_end(stokes_ctx* c, bool open) {
+    if (!open) return STOKES_OK;
     HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
     c->ev_used += 2;
     return STOKES_OK;
 }
 
 stokes_status collect_timing(stokes_ctx* c) {
-    if (!c->timing || c->ev_used == 0) return STOKES_OK;
+    if (c->ev_used == 0) return STOKES_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]));
-        c->timing_ms += ms;
-        c->timing_launches += 1;
+        c->timing_ms[c->ev_kind[q]] += ms;
+        c->timing_launches[c->ev_kind[q]] += 1;
     }
     c->ev_used = 0;
     return STOKES_OK;
@@ -184,29 +207,38 @@ stokes_status read_state(stokes_ctx* c, int which, CgState* out) {
 
 int first_batch(stokes_ctx* c, int which) {
     if (c->check_every > 0) return c->check_every;
-    return c->last_it[which] > 0 ? std::max(1, c->last_it[which] - 1) : 16;
+    return c->last_it[which] > 0 ? std::max(1, c->last_it[which]) : 16;
 }
 
 int next_batch(stokes_ctx* c) { return c->check_every > 0 ? c->check_every : 4; }
 
 // Solve A x = b on the faces (b == nullptr: the uniform force).  x -> c->fx.
+// Iteration j launches the dir, stencil and update kernels; the host polls the
+// device state between batches.
 stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
     CgState* st = c->cg + 0;
     hipLaunchKernelGGL(k_cgA_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0], c->force[1],
-                       c->force[2], c->fx, c->fr, c->fd, st, c->red, eps, c->max_inner);
+                       c->force[2], c->fx, c->fr, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     int batch = first_batch(c, 0);
+    int j = 0;
     CgState h{};
     for (;;) {
-        for (int t = 0; t < batch; ++t) {
-            ST_TRY(time_begin(c));
+        for (int t = 0; t < batch; ++t, ++j) {
+            bool open;
+            ST_TRY(time_begin(c, kTimeADir, &open));
+            hipLaunchKernelGGL(k_cgA_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->fd, st,
+                               c->part, j);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeAStencil, &open));
             hipLaunchKernelGGL(k_cgA_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fd, c->fq, st,
-                               c->red);
-            ST_TRY(time_end(c));
+                               c->part);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeAUpdate, &open));
             hipLaunchKernelGGL(k_cgA_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fx, c->fr, c->fd,
-                               c->fq, st, c->red);
-            hipLaunchKernelGGL(k_cgA_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->fd, st);
+                               c->fq, st, c->part, j);
+            ST_TRY(time_end(c, open));
         }
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(c, 0, &h));
@@ -223,18 +255,27 @@ stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* 
 stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
     CgState* st = c->cg + 1;
-    hipLaunchKernelGGL(k_cgS_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->zs, c->sr, c->sd, st,
-                       c->red, eps, c->max_inner);
+    hipLaunchKernelGGL(k_cgS_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, b, c->zs, c->sr, st, c->part,
+                       eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     int batch = first_batch(c, 1);
+    int j = 0;
     CgState h{};
     for (;;) {
-        for (int t = 0; t < batch; ++t) {
+        for (int t = 0; t < batch; ++t, ++j) {
+            bool open;
+            ST_TRY(time_begin(c, kTimeSDir, &open));
+            hipLaunchKernelGGL(k_cgS_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, c->sr, c->sd, st,
+                               c->part, j);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeSStencil, &open));
             hipLaunchKernelGGL(k_cgS_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->sd, c->sq, st,
-                               c->red);
-            hipLaunchKernelGGL(k_cgS_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->zs, c->sr, c->sd,
-                               c->sq, st, c->red);
-            hipLaunchKernelGGL(k_cgS_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->sr, c->sd, st);
+                               c->part);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeSUpdate, &open));
+            hipLaunchKernelGGL(k_cgS_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, c->zs, c->sr, c->sd,
+                               c->sq, st, c->part, j);
+            ST_TRY(time_end(c, open));
         }
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(c, 1, &h));
@@ -264,27 +305,29 @@ stokes_status project(stokes_ctx* c, double* x) {
     return STOKES_OK;
 }
 
-stokes_status dots(stokes_ctx* c, const double* a0, const double* b0, const double* a1, const double* b1,
-                   const double* a2, const double* b2, double out[3]) {
-    hipLaunchKernelGGL(k_dots, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, a0, b0, a1, b1, a2, b2, c->red);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->host_out, c->red.out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+// per-block partials [3 * nblk] to the host, added there in block order
+stokes_status host_totals(stokes_ctx* c, double out[3]) {
+    const int nb = c->sw.nblk;
+    HIP_TRY(hipMemcpyAsync(c->host_part, c->dpart, (size_t)3 * nb * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    out[0] = c->host_out[0];
-    out[1] = c->host_out[1];
-    out[2] = c->host_out[2];
+    out[0] = out[1] = out[2] = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 3; ++q) out[q] += c->host_part[3 * b + q];
     return STOKES_OK;
 }
 
-stokes_status face_sums(stokes_ctx* c, const double* u, double out[3]) {
-    hipLaunchKernelGGL(k_face_sums, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, u, c->red);
+stokes_status dots(stokes_ctx* c, const double* a0, const double* b0, const double* a1, const double* b1,
+                   const double* a2, const double* b2, double out[3]) {
+    hipLaunchKernelGGL(k_dots, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, a0, b0, a1, b1, a2, b2, c->dpart);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->host_out, c->red.out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    out[0] = c->host_out[0];
-    out[1] = c->host_out[1];
-    out[2] = c->host_out[2];
-    return STOKES_OK;
+    return host_totals(c, out);
+}
+
+stokes_status face_sums(stokes_ctx* c, const double* u, double out[3]) {
+    hipLaunchKernelGGL(k_face_sums, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, u, c->dpart);
+    HIP_TRY(hipGetLastError());
+    return host_totals(c, out);
 }
 
 // permeability (voxel units) along the force from face sums
@@ -373,7 +416,7 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
 
     const int N = c->N;
     const int64_t n3 = c->n3;
-    c->sw = make_sweep(N);
+    c->sw = make_sweep(N, c->sweep_blocks);
     if (c->sw.nblk > kMaxBlocks) return STOKES_E_LIMIT;
     c->wpr = (N + 31) / 32;
 
@@ -390,15 +433,15 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     ST_TRY(dev_alloc(c, &c->comp_part, (size_t)kCompBlocks * K));
     ST_TRY(dev_alloc(c, &c->comp_mean, (size_t)K));
     if (g.ncomp_kept > 1) ST_TRY(dev_alloc(c, &c->label, (size_t)n3));
-    for (double** f : {&c->fx, &c->fr, &c->fd, &c->fq, &c->u}) ST_TRY(dev_alloc(c, f, (size_t)(3 * n3)));
-    for (double** v : {&c->p, &c->r, &c->zs, &c->d, &c->q, &c->sr, &c->sd, &c->sq})
+    for (double** f : {&c->fx, &c->fr, &c->fq, &c->u, &c->fd})
+        ST_TRY(dev_alloc(c, f, (size_t)(3 * n3)));
+    for (double** v : {&c->p, &c->r, &c->zs, &c->d, &c->q, &c->sr, &c->sq, &c->invdS, &c->sd})
         ST_TRY(dev_alloc(c, v, (size_t)n3));
     ST_TRY(dev_alloc(c, &c->cg, 2));
-    ST_TRY(dev_alloc(c, &c->red.part, (size_t)kMaxParts * kMaxBlocks));
-    ST_TRY(dev_alloc(c, &c->red.ticket, 1));
-    ST_TRY(dev_alloc(c, &c->red.out, 8));
+    ST_TRY(dev_alloc(c, &c->part, (size_t)kNumSlots * kMaxBlocks));
+    ST_TRY(dev_alloc(c, &c->dpart, (size_t)3 * kMaxBlocks));
     if (hipHostMalloc((void**)&c->host_state, sizeof(CgState)) != hipSuccess) return STOKES_E_NOMEM;
-    if (hipHostMalloc((void**)&c->host_out, 8 * sizeof(double)) != hipSuccess) return STOKES_E_NOMEM;
+    if (hipHostMalloc((void**)&c->host_part, 3 * kMaxBlocks * sizeof(double)) != hipSuccess) return STOKES_E_NOMEM;
 
     std::vector<double> counts(K, 0.0);
     for (int q = 0; q < g.ncomp_kept; ++q) counts[q] = (double)g.comp_size[q];
@@ -407,10 +450,15 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     if (c->label)
         HIP_TRY(hipMemcpyAsync(c->label, g.label.data(), (size_t)n3 * sizeof(uint16_t), hipMemcpyHostToDevice,
                                c->stream));
-    HIP_TRY(hipMemsetAsync(c->red.ticket, 0, sizeof(unsigned), c->stream));
     HIP_TRY(hipMemsetAsync(c->p, 0, (size_t)n3 * sizeof(double), c->stream));
     HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+    // zero every work vector once so that inactive entries start at 0
+    for (double* f : {c->fx, c->fr, c->fq, c->fd})
+        HIP_TRY(hipMemsetAsync(f, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+    for (double* v : {c->r, c->zs, c->d, c->q, c->sr, c->sq, c->sd})
+        HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(double), c->stream));
     hipLaunchKernelGGL(k_face_codes, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->bits, c->wpr, c->code);
+    hipLaunchKernelGGL(k_inv_diag_Shat, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->invdS);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));  // the host vectors above go out of scope
 
@@ -514,8 +562,18 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "max_inner") { if (v < 1 || v > 1e8) return STOKES_E_ARG; c->max_inner = (int)v; }
     else if (k == "stop_prec") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->stop_prec = (int)v; }
     else if (k == "check_every") { if (v < 0 || v > 4096) return STOKES_E_ARG; c->check_every = (int)v; }
-    else if (k == "kernel_timing") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->timing = v != 0.0; }
+    else if (k == "kernel_timing") {
+        if (v < 0 || v > 1e6 || v != std::floor(v)) return STOKES_E_ARG;
+        c->timing = (int)v;
+    }
     else if (k == "true_velocity") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->true_velocity = (int)v; }
+    else if (k == "sweep_blocks") {
+        if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
+        const Sweep sw = make_sweep(c->N, (int)v);
+        if (sw.nblk > kMaxBlocks) return STOKES_E_ARG;
+        c->sweep_blocks = (int)v;
+        c->sw = sw;
+    }
     else return STOKES_E_ARG;
     return STOKES_OK;
 }
@@ -800,14 +858,15 @@ stokes_status stokes_info(stokes_ctx* c, int64_t info[12]) {
     return STOKES_OK;
 }
 
-stokes_status stokes_kernel_timing(stokes_ctx* c, double* ms_total, int64_t* launches, int64_t* cells) {
-    if (!c || !ms_total || !launches || !cells) return STOKES_E_ARG;
+stokes_status stokes_kernel_timing(stokes_ctx* c, int kernel, double* ms_total, int64_t* launches,
+                                   double* bytes_per_launch) {
+    if (!c || !ms_total || !launches || !bytes_per_launch || kernel < 0 || kernel >= kTimeKinds) return STOKES_E_ARG;
     ST_TRY(collect_timing(c));
-    *ms_total = c->timing_ms;
-    *launches = c->timing_launches;
-    *cells = c->n3;
-    c->timing_ms = 0.0;
-    c->timing_launches = 0;
+    *ms_total = c->timing_ms[kernel];
+    *launches = c->timing_launches[kernel];
+    *bytes_per_launch = kBytesPerCell[kernel] * (double)c->n3;
+    c->timing_ms[kernel] = 0.0;
+    c->timing_launches[kernel] = 0;
     return STOKES_OK;
 }
 

@@ -89,7 +89,7 @@ def load():
         "stokes_apply": ([vp, ip, vp, vp], ip),
         "stokes_apply_device": ([vp, ip, vp, vp], ip),
         "stokes_info": ([vp, i64p], ip),
-        "stokes_kernel_timing": ([vp, dp, i64p, i64p], ip),
+        "stokes_kernel_timing": ([vp, ip, dp, i64p, dp], ip),
         "stokes_destroy": ([vp], None),
         "stokes_status_str": ([ip], ctypes.c_char_p),
         "stokes_preprocess": ([vp, ip, dp, ctypes.c_uint, i64p, vp, vp], ip),
@@ -221,13 +221,17 @@ def stokes_info(ctx):
     return {k: int(info[i]) for i, k in enumerate(keys)}
 
 
-def stokes_kernel_timing(ctx):
+KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil", "k_cgS_update"]
+
+
+def stokes_kernel_timing(ctx, kernel):
+    """(total ms, launches, algorithmic bytes per launch) of one inner-loop kernel."""
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    cells = ctypes.c_int64()
-    _check(load().stokes_kernel_timing(ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cells)),
+    nbytes = ctypes.c_double()
+    _check(load().stokes_kernel_timing(ctx, int(kernel), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(nbytes)),
            "stokes_kernel_timing")
-    return ms.value, n.value, cells.value
+    return ms.value, n.value, nbytes.value
 
 
 def stokes_destroy(ctx):
@@ -277,8 +281,8 @@ class Stokes:
     def info(self):
         return stokes_info(self._ctx)
 
-    def kernel_timing(self):
-        return stokes_kernel_timing(self._ctx)
+    def kernel_timing(self, kernel):
+        return stokes_kernel_timing(self._ctx, kernel)
 
     def close(self):
         if getattr(self, "_ctx", None):
