@@ -31,6 +31,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, N):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary,
+    or None when that summary was taken at another size or on other kernel code."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_128_spheres_inner_cg.md")
+    src = os.path.join(ROOT, "paper_2307_05266_amd", "csrc", "kernels.h")
+    try:
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        table = json.loads(m.group(1))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, AttributeError, ValueError):
+        return None
+    if table.get("kernels_sha256_16") != h or table.get("N") != N:
+        return None
+    entry = table["per_launch"].get(kernel)
+    return entry["traffic_bytes"] if entry else None
+
+
 def cpu_baseline(mask, gpu_rep, budget_s=20.0):
     """Time the oracle on a bounded sample of the same workload and scale it to
     one solve: one inner A solve (u0 = A^-1 f) and a capped run of inner SIMPLE
@@ -74,6 +93,10 @@ def main():
     ap.add_argument("--precond", default="simple", choices=["simple", "uzawa"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-blocks", type=int, default=0)
+    ap.add_argument("--max-outer", type=int, default=0,
+                    help="cap the outer iterations (short runs for hardware-counter profiles)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this solver has no multi-GPU path",
@@ -101,6 +124,15 @@ def main():
     setup_ms = (time.perf_counter() - t0) * 1e3
     if args.sweep_blocks:
         s.set_option("sweep_blocks", args.sweep_blocks)
+    if args.max_outer:
+        s.set_option("max_outer", args.max_outer)
+    if args.copy_calibration:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     info = s.info()
     log(f"[bench] setup {setup_ms:.1f} ms, fluid {info['nfluid']} components {info['ncomp_kept']}")
 
@@ -177,7 +209,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom, N),
             "launches": kernels[dom]["launches"],
             "avg_launch_us": kernels[dom]["avg_launch_us"],
             "bytes_per_launch": kernels[dom]["bytes_per_launch"],

@@ -40,6 +40,10 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxBlocks = 4096;      // partial slots per reduced quantity
 constexpr int kMaxCompLds = 2048;     // components handled by the projection kernels
 
+// z-planes whose loads a thread issues together before computing them
+constexpr int kZBatch = 4;     // cell kernels
+constexpr int kZBatchA = 2;    // face kernels (three planes of unknowns per voxel)
+
 // partial slots of the inner CG loops
 constexpr int kRZ = 0, kZZ = 1, kDQ = 2, kNumSlots = 3;
 
@@ -502,15 +506,34 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const doubl
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const bool first = j == 0;
-    for (int k = c.k0; k < c.k1; ++k) {
-        const int X = c.X0 + k * s.N2;
-        const int cd = code[X];
-        const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+    for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
+        // loads of up to kZBatch planes first, so they are in flight together
+        double rv[kZBatch][3], dv[kZBatch][3];
+        int cd[kZBatch];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const size_t F = (size_t)a * s.n3 + X;
-            const double z = r[F] * inv_diag_A(sc[a]);
-            d[F] = first ? z : z + beta * d[F];
+        for (int u = 0; u < kZBatch; ++u) {
+            // planes past the run re-read the first plane; their results are dropped
+            const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
+            cd[u] = code[X];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                rv[u][a] = r[(size_t)a * s.n3 + X];
+                dv[u][a] = d[(size_t)a * s.n3 + X];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kZBatch; ++u) {
+            const bool in = k0 + u < c.k1;
+            const int X = c.X0 + (in ? k0 + u : c.k0) * s.N2;
+            const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
+            double dn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double z = rv[u][a] * inv_diag_A(sc[a]);
+                dn[a] = first ? z : z + beta * dv[u][a];
+            }
+            if (in)
+                for (int a = 0; a < 3; ++a) d[(size_t)a * s.n3 + X] = dn[a];
         }
     }
 }
@@ -522,16 +545,37 @@ __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const d
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid) {
-        for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s, c, k);
-            const int cd = code[n.X];
-            const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatchA) {
+            double v[kZBatchA][3][7];
+            int cd[kZBatchA];
+            Nbr nb[kZBatchA];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double* __restrict__ da = d + (size_t)a * s.n3;
-                const double v = sc[a] ? apply_A_face(da, n, sc[a]) : 0.0;
-                q[(size_t)a * s.n3 + n.X] = v;
-                acc[0] += da[n.X] * v;
+            for (int u = 0; u < kZBatchA; ++u) {
+                // planes past the run re-read the first plane; their results are dropped
+                nb[u] = neighbours(s, c, k0 + u < c.k1 ? k0 + u : c.k0);
+                cd[u] = code[nb[u].X];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double* __restrict__ da = d + (size_t)a * s.n3;
+                    const int idx[7] = {nb[u].X, nb[u].xm, nb[u].xp, nb[u].ym, nb[u].yp, nb[u].zm, nb[u].zp};
+#pragma unroll
+                    for (int t = 0; t < 7; ++t) v[u][a][t] = da[idx[t]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kZBatchA; ++u) {
+                const bool in = k0 + u < c.k1;
+                const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
+                double qv[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double* w = v[u][a];
+                    const double nbs = ((w[1] + w[2]) + (w[3] + w[4])) + (w[5] + w[6]);
+                    qv[a] = sc[a] ? (double)(5 + sc[a]) * w[0] - nbs : 0.0;
+                    acc[0] += in ? w[0] * qv[a] : 0.0;
+                }
+                if (in)
+                    for (int a = 0; a < 3; ++a) q[(size_t)a * s.n3 + nb[u].X] = qv[a];
             }
         }
     }
@@ -547,19 +591,41 @@ __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, double* 
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
-        for (int k = c.k0; k < c.k1; ++k) {
-            const int X = c.X0 + k * s.N2;
-            const int cd = code[X];
-            const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatchA) {
+            double xv[kZBatchA][3], rv[kZBatchA][3], dv[kZBatchA][3], qv[kZBatchA][3];
+            int cd[kZBatchA];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const size_t F = (size_t)a * s.n3 + X;
-                x[F] += alpha * d[F];
-                const double rn = r[F] - alpha * q[F];
-                r[F] = rn;
-                const double z = rn * inv_diag_A(sc[a]);
-                acc[0] += rn * z;
-                acc[1] += z * z;
+            for (int u = 0; u < kZBatchA; ++u) {
+                const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
+                cd[u] = code[X];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const size_t F = (size_t)a * s.n3 + X;
+                    xv[u][a] = x[F];
+                    rv[u][a] = r[F];
+                    dv[u][a] = d[F];
+                    qv[u][a] = q[F];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kZBatchA; ++u) {
+                const bool in = k0 + u < c.k1;
+                const int X = c.X0 + (in ? k0 + u : c.k0) * s.N2;
+                const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
+                double xn[3], rn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    xn[a] = xv[u][a] + alpha * dv[u][a];
+                    rn[a] = rv[u][a] - alpha * qv[u][a];
+                    const double z = rn[a] * inv_diag_A(sc[a]);
+                    acc[0] += in ? rn[a] * z : 0.0;
+                    acc[1] += in ? z * z : 0.0;
+                }
+                if (in)
+                    for (int a = 0; a < 3; ++a) {
+                        x[(size_t)a * s.n3 + X] = xn[a];
+                        r[(size_t)a * s.n3 + X] = rn[a];
+                    }
             }
         }
     }
@@ -601,10 +667,21 @@ __global__ void k_cgS_dir(Sweep s, const double* __restrict__ invd, const double
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const bool first = j == 0;
-    for (int k = c.k0; k < c.k1; ++k) {
-        const int X = c.X0 + k * s.N2;
-        const double z = r[X] * invd[X];
-        d[X] = first ? z : z + beta * d[X];
+    for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
+        double rv[kZBatch], iv[kZBatch], dv[kZBatch];
+#pragma unroll
+        for (int u = 0; u < kZBatch; ++u) {
+            const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
+            rv[u] = r[X];
+            iv[u] = invd[X];
+            dv[u] = d[X];
+        }
+#pragma unroll
+        for (int u = 0; u < kZBatch; ++u) {
+            const double z = rv[u] * iv[u];
+            const double dn = first ? z : z + beta * dv[u];
+            if (k0 + u < c.k1) d[c.X0 + (k0 + u) * s.N2] = dn;
+        }
     }
 }
 
@@ -615,13 +692,33 @@ __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const d
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid) {
-        for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s, c, k);
-            const double dX = d[n.X];
-            const double v =
-                apply_Shat_cell(dX, d[n.xm], d[n.xp], d[n.ym], d[n.yp], d[n.zm], d[n.zp], code, n, code[n.X]);
-            q[n.X] = v;
-            acc[0] += dX * v;
+        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
+            double v[kZBatch][7];
+            int cX[kZBatch], cxp[kZBatch], cyp[kZBatch], czp[kZBatch];
+            Nbr nb[kZBatch];
+#pragma unroll
+            for (int u = 0; u < kZBatch; ++u) {
+                nb[u] = neighbours(s, c, k0 + u < c.k1 ? k0 + u : c.k0);
+                const Nbr& n = nb[u];
+                const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
+#pragma unroll
+                for (int t = 0; t < 7; ++t) v[u][t] = d[idx[t]];
+                cX[u] = code[n.X];
+                cxp[u] = code[n.xp];
+                cyp[u] = code[n.yp];
+                czp[u] = code[n.zp];
+            }
+#pragma unroll
+            for (int u = 0; u < kZBatch; ++u) {
+                const bool in = k0 + u < c.k1;
+                const double* w = v[u];
+                const double dX = w[0];
+                const double qv = ((inv_diag_A(sx_of(cX[u])) * (dX - w[1]) + inv_diag_A(sx_of(cxp[u])) * (dX - w[2])) +
+                                   (inv_diag_A(sy_of(cX[u])) * (dX - w[3]) + inv_diag_A(sy_of(cyp[u])) * (dX - w[4]))) +
+                                  (inv_diag_A(sz_of(cX[u])) * (dX - w[5]) + inv_diag_A(sz_of(czp[u])) * (dX - w[6]));
+                acc[0] += in ? dX * qv : 0.0;
+                if (in) q[nb[u].X] = qv;
+            }
         }
     }
     write_partials<1>(acc, part, kDQ, c.lb);
@@ -636,14 +733,31 @@ __global__ void k_cgS_update(Sweep s, const double* __restrict__ invd, double* _
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
-        for (int k = c.k0; k < c.k1; ++k) {
-            const int X = c.X0 + k * s.N2;
-            x[X] += alpha * d[X];
-            const double rn = r[X] - alpha * q[X];
-            r[X] = rn;
-            const double z = rn * invd[X];
-            acc[0] += rn * z;
-            acc[1] += z * z;
+        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
+            double xv[kZBatch], rv[kZBatch], dv[kZBatch], qv[kZBatch], iv[kZBatch];
+#pragma unroll
+            for (int u = 0; u < kZBatch; ++u) {
+                const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
+                xv[u] = x[X];
+                rv[u] = r[X];
+                dv[u] = d[X];
+                qv[u] = q[X];
+                iv[u] = invd[X];
+            }
+#pragma unroll
+            for (int u = 0; u < kZBatch; ++u) {
+                const bool in = k0 + u < c.k1;
+                const double xn = xv[u] + alpha * dv[u];
+                const double rn = rv[u] - alpha * qv[u];
+                const double z = rn * iv[u];
+                acc[0] += in ? rn * z : 0.0;
+                acc[1] += in ? z * z : 0.0;
+                if (in) {
+                    const int X = c.X0 + (k0 + u) * s.N2;
+                    x[X] = xn;
+                    r[X] = rn;
+                }
+            }
         }
     }
     write_partials<2>(acc, part, kRZ, c.lb);
