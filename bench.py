@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--precond", default="simple", choices=["simple", "uzawa"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed mixed-precision solves reported beside the FP64 line (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-blocks", type=int, default=0)
     ap.add_argument("--max-outer", type=int, default=0,
@@ -124,6 +127,8 @@ def main():
     setup_ms = (time.perf_counter() - t0) * 1e3
     if args.sweep_blocks:
         s.set_option("sweep_blocks", args.sweep_blocks)
+    if args.precision == "mixed":
+        s.set_option("precision", 1)
     if args.max_outer:
         s.set_option("max_outer", args.max_outer)
     if args.copy_calibration:
@@ -188,15 +193,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"FP64 {args.precond.upper()} solve, {N}^3 periodic overlapping spheres r=6 porosity 0.5 "
-                        "seed 0, force x, tol 1e-8, inner 1e-12",
-            "N": N, "precond": args.precond, "tol": 1e-8, "eps_inner": 1e-12,
+            "workload": (f"{'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'} {args.precond.upper()} solve, "
+                         f"{N}^3 periodic overlapping spheres r=6 porosity 0.5 seed 0, force x, tol 1e-8"),
+            "N": N, "precond": args.precond, "precision": args.precision, "tol": 1e-8,
         },
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
         "k_hat": rep["k_hat"],
+        "div_norm": rep["div_norm"],
         "outer_iters": rep["outer_iters"],
         "inner_A_iters": sweeps_A,
         "inner_S_iters": sweeps_S,
@@ -216,6 +222,26 @@ def main():
         },
         "kernels": kernels,
     }
+    if args.precision == "fp64" and args.mixed_steps > 0:
+        # the same solve with FP32 inner solves and FP64 outer recurrences
+        k64, div64 = rep["k_hat"], rep["div_norm"]
+        s.set_option("precision", 1)
+        rm = s.solve(pc, 1e-8)  # warm-up (allocates the FP32 vectors)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            rm = s.solve(pc, 1e-8)
+        torch.cuda.synchronize()
+        tm = (time.perf_counter() - t0) / args.mixed_steps
+        out["mixed_vs_fp64"] = {
+            "value": 1.0 / tm, "unit": "solves/s", "ms_per_solve": tm * 1e3,
+            "speedup_vs_fp64": (1.0 / tm) / value,
+            "k_hat": rm["k_hat"], "k_rel_diff_vs_fp64": abs(rm["k_hat"] - k64) / abs(k64),
+            "div_norm": rm["div_norm"], "div_norm_fp64": div64, "rel_res": rm["rel_res"],
+            "outer_iters": rm["outer_iters"], "inner_A_iters": rm["inner_A_iters"],
+            "inner_S_iters": rm["inner_S_iters"],
+        }
+        log(f"[bench] mixed: {tm:.3f} s/solve outer={rm['outer_iters']} k={rm['k_hat']:.12e}")
     s.close()
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")

@@ -154,6 +154,14 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 HIP events (0 = off, the default)
  *   "true_velocity" 1: after the solve, recompute u = A^{-1}(f - B^T p)
  *   "sweep_blocks" number of workgroups a sweep aims for (default 1024)
+ *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
+ *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
+ *                 in FP64), outer flexible CG, true residual and permeability
+ *                 in FP64, defect-correction cycles with the velocity refined
+ *                 in FP64 (the paper's remarks on inexact inner solves, Sec. 3.2)
+ *   "eps_A32", "eps_S32"  FP32 inner tolerances of the mixed path (default 1e-5)
+ *   "cycle_rtol"  residual reduction per defect-correction cycle (default 1e-4)
+ *   "eps_refine"  relative residual of the FP64 velocity refinement (default 1e-12)
  * Unknown keys or out-of-range values give STOKES_E_ARG.
  */
 stokes_status stokes_set_option(stokes_ctx *ctx, const char *key, double value);

@@ -458,12 +458,26 @@ __device__ __forceinline__ bool cg_update_scalars(CgState* st, const double* par
     return false;
 }
 
+// The inner-CG kernels are templates on the storage and arithmetic type T of
+// x, r, d, q (double, or float for the mixed-precision path); partial dot
+// products are always accumulated in double.
+template <class T>
+__device__ __forceinline__ T inv_diag_A_t(int s) {
+    T v = T(0);
+    v = s == 1 ? T(1.0 / 6.0) : v;
+    v = s == 2 ? T(1.0 / 7.0) : v;
+    v = s == 3 ? T(1.0 / 8.0) : v;
+    v = s == 4 ? T(1.0 / 9.0) : v;
+    v = s == 5 ? T(1.0 / 10.0) : v;
+    return v;
+}
+
 // ---- A (faces), Jacobi diag(A) = 5 + s -------------------------------------
 // x = 0, r = b (b == nullptr: the uniform force on active faces); partials of
-// (r, z), (z, z) with z = D^-1 r.
+// (r, z), (z, z) with z = D^-1 r.  b is always an FP64 vector of the outer loop.
+template <class T>
 __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const double* b, double f0, double f1,
-                           double f2, double* __restrict__ x, double* r, CgState* st, double* part, double eps,
-                           int maxit) {
+                           double f2, T* __restrict__ x, T* r, CgState* st, double* part, double eps, int maxit) {
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
@@ -475,12 +489,12 @@ __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const doub
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const size_t F = (size_t)a * s.n3 + X;
-                const double bv = sc[a] ? (b ? b[F] : fc[a]) : 0.0;
-                const double z = bv * inv_diag_A(sc[a]);
-                x[F] = 0.0;
+                const T bv = (T)(sc[a] ? (b ? b[F] : fc[a]) : 0.0);
+                const T z = bv * inv_diag_A_t<T>(sc[a]);
+                x[F] = T(0);
                 r[F] = bv;
-                acc[0] += bv * z;
-                acc[1] += z * z;
+                acc[0] += (double)bv * (double)z;
+                acc[1] += (double)z * (double)z;
             }
         }
     }
@@ -498,17 +512,19 @@ __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const doub
 // plane a's face state from a voxel's code
 __device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(code) : (a == 1 ? sy_of(code) : sz_of(code)); }
 
-__global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ r,
-                          double* __restrict__ d, CgState* st, double* part, int j) {
+template <class T>
+__global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ r, T* __restrict__ d,
+                          CgState* st, double* part, int j) {
     if (st->done) return;
-    double beta;
-    if (cg_dir_scalars(st, part, s.nblk, j, &beta)) return;
+    double beta_d;
+    if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
+    const T beta = (T)beta_d;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const bool first = j == 0;
     for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
         // loads of up to kZBatch planes first, so they are in flight together
-        double rv[kZBatch][3], dv[kZBatch][3];
+        T rv[kZBatch][3], dv[kZBatch][3];
         int cd[kZBatch];
 #pragma unroll
         for (int u = 0; u < kZBatch; ++u) {
@@ -526,10 +542,10 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const doubl
             const bool in = k0 + u < c.k1;
             const int X = c.X0 + (in ? k0 + u : c.k0) * s.N2;
             const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
-            double dn[3];
+            T dn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double z = rv[u][a] * inv_diag_A(sc[a]);
+                const T z = rv[u][a] * inv_diag_A_t<T>(sc[a]);
                 dn[a] = first ? z : z + beta * dv[u][a];
             }
             if (in)
@@ -539,14 +555,15 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const doubl
 }
 
 // q = A d on the faces and the partial (d, q)
-__global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ d,
-                              double* __restrict__ q, CgState* st, double* part) {
+template <class T>
+__global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,
+                              CgState* st, double* part) {
     if (st->done) return;
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid) {
         for (int k0 = c.k0; k0 < c.k1; k0 += kZBatchA) {
-            double v[kZBatchA][3][7];
+            T v[kZBatchA][3][7];
             int cd[kZBatchA];
             Nbr nb[kZBatchA];
 #pragma unroll
@@ -556,7 +573,7 @@ __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const d
                 cd[u] = code[nb[u].X];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double* __restrict__ da = d + (size_t)a * s.n3;
+                    const T* __restrict__ da = d + (size_t)a * s.n3;
                     const int idx[7] = {nb[u].X, nb[u].xm, nb[u].xp, nb[u].ym, nb[u].yp, nb[u].zm, nb[u].zp};
 #pragma unroll
                     for (int t = 0; t < 7; ++t) v[u][a][t] = da[idx[t]];
@@ -566,13 +583,13 @@ __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const d
             for (int u = 0; u < kZBatchA; ++u) {
                 const bool in = k0 + u < c.k1;
                 const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
-                double qv[3];
+                T qv[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double* w = v[u][a];
-                    const double nbs = ((w[1] + w[2]) + (w[3] + w[4])) + (w[5] + w[6]);
-                    qv[a] = sc[a] ? (double)(5 + sc[a]) * w[0] - nbs : 0.0;
-                    acc[0] += in ? w[0] * qv[a] : 0.0;
+                    const T* w = v[u][a];
+                    const T nbs = ((w[1] + w[2]) + (w[3] + w[4])) + (w[5] + w[6]);
+                    qv[a] = sc[a] ? (T)(5 + sc[a]) * w[0] - nbs : T(0);
+                    acc[0] += in ? (double)w[0] * (double)qv[a] : 0.0;
                 }
                 if (in)
                     for (int a = 0; a < 3; ++a) q[(size_t)a * s.n3 + nb[u].X] = qv[a];
@@ -582,17 +599,18 @@ __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const d
     write_partials<1>(acc, part, kDQ, c.lb);
 }
 
-__global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ x,
-                             double* __restrict__ r, const double* __restrict__ d, const double* __restrict__ q,
-                             CgState* st, double* part, int j) {
+template <class T>
+__global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __restrict__ x, T* __restrict__ r,
+                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part, int j) {
     if (st->done) return;
-    double alpha;
-    if (cg_update_scalars(st, part, s.nblk, j, &alpha)) return;
+    double alpha_d;
+    if (cg_update_scalars(st, part, s.nblk, j, &alpha_d)) return;
+    const T alpha = (T)alpha_d;
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k0 = c.k0; k0 < c.k1; k0 += kZBatchA) {
-            double xv[kZBatchA][3], rv[kZBatchA][3], dv[kZBatchA][3], qv[kZBatchA][3];
+            T xv[kZBatchA][3], rv[kZBatchA][3], dv[kZBatchA][3], qv[kZBatchA][3];
             int cd[kZBatchA];
 #pragma unroll
             for (int u = 0; u < kZBatchA; ++u) {
@@ -612,14 +630,14 @@ __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, double* 
                 const bool in = k0 + u < c.k1;
                 const int X = c.X0 + (in ? k0 + u : c.k0) * s.N2;
                 const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
-                double xn[3], rn[3];
+                T xn[3], rn[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     xn[a] = xv[u][a] + alpha * dv[u][a];
                     rn[a] = rv[u][a] - alpha * qv[u][a];
-                    const double z = rn[a] * inv_diag_A(sc[a]);
-                    acc[0] += in ? rn[a] * z : 0.0;
-                    acc[1] += in ? z * z : 0.0;
+                    const T z = rn[a] * inv_diag_A_t<T>(sc[a]);
+                    acc[0] += in ? (double)rn[a] * (double)z : 0.0;
+                    acc[1] += in ? (double)z * (double)z : 0.0;
                 }
                 if (in)
                     for (int a = 0; a < 3; ++a) {
@@ -633,19 +651,20 @@ __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, double* 
 }
 
 // ---- SIMPLE matrix (cells), Jacobi with the precomputed inverse diagonal ----
-__global__ void k_cgS_init(Sweep s, const double* __restrict__ invd, const double* b, double* __restrict__ x,
-                           double* r, CgState* st, double* part, double eps, int maxit) {
+template <class T>
+__global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b, T* __restrict__ x, T* r,
+                           CgState* st, double* part, double eps, int maxit) {
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k = c.k0; k < c.k1; ++k) {
             const int X = c.X0 + k * s.N2;
-            const double bv = b[X];
-            const double z = bv * invd[X];
-            x[X] = 0.0;
+            const T bv = (T)b[X];
+            const T z = bv * invd[X];
+            x[X] = T(0);
             r[X] = bv;
-            acc[0] += bv * z;
-            acc[1] += z * z;
+            acc[0] += (double)bv * (double)z;
+            acc[1] += (double)z * (double)z;
         }
     }
     write_partials<2>(acc, part, kRZ, c.lb);
@@ -659,16 +678,18 @@ __global__ void k_cgS_init(Sweep s, const double* __restrict__ invd, const doubl
     }
 }
 
-__global__ void k_cgS_dir(Sweep s, const double* __restrict__ invd, const double* __restrict__ r,
-                          double* __restrict__ d, CgState* st, double* part, int j) {
+template <class T>
+__global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restrict__ r, T* __restrict__ d,
+                          CgState* st, double* part, int j) {
     if (st->done) return;
-    double beta;
-    if (cg_dir_scalars(st, part, s.nblk, j, &beta)) return;
+    double beta_d;
+    if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
+    const T beta = (T)beta_d;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const bool first = j == 0;
     for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
-        double rv[kZBatch], iv[kZBatch], dv[kZBatch];
+        T rv[kZBatch], iv[kZBatch], dv[kZBatch];
 #pragma unroll
         for (int u = 0; u < kZBatch; ++u) {
             const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
@@ -678,22 +699,23 @@ __global__ void k_cgS_dir(Sweep s, const double* __restrict__ invd, const double
         }
 #pragma unroll
         for (int u = 0; u < kZBatch; ++u) {
-            const double z = rv[u] * iv[u];
-            const double dn = first ? z : z + beta * dv[u];
+            const T z = rv[u] * iv[u];
+            const T dn = first ? z : z + beta * dv[u];
             if (k0 + u < c.k1) d[c.X0 + (k0 + u) * s.N2] = dn;
         }
     }
 }
 
 // q = Shat d on the cells and the partial (d, q)
-__global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ d,
-                              double* __restrict__ q, CgState* st, double* part) {
+template <class T>
+__global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,
+                              CgState* st, double* part) {
     if (st->done) return;
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid) {
         for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
-            double v[kZBatch][7];
+            T v[kZBatch][7];
             int cX[kZBatch], cxp[kZBatch], cyp[kZBatch], czp[kZBatch];
             Nbr nb[kZBatch];
 #pragma unroll
@@ -711,12 +733,15 @@ __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const d
 #pragma unroll
             for (int u = 0; u < kZBatch; ++u) {
                 const bool in = k0 + u < c.k1;
-                const double* w = v[u];
-                const double dX = w[0];
-                const double qv = ((inv_diag_A(sx_of(cX[u])) * (dX - w[1]) + inv_diag_A(sx_of(cxp[u])) * (dX - w[2])) +
-                                   (inv_diag_A(sy_of(cX[u])) * (dX - w[3]) + inv_diag_A(sy_of(cyp[u])) * (dX - w[4]))) +
-                                  (inv_diag_A(sz_of(cX[u])) * (dX - w[5]) + inv_diag_A(sz_of(czp[u])) * (dX - w[6]));
-                acc[0] += in ? dX * qv : 0.0;
+                const T* w = v[u];
+                const T dX = w[0];
+                const T qv = ((inv_diag_A_t<T>(sx_of(cX[u])) * (dX - w[1]) +
+                               inv_diag_A_t<T>(sx_of(cxp[u])) * (dX - w[2])) +
+                              (inv_diag_A_t<T>(sy_of(cX[u])) * (dX - w[3]) +
+                               inv_diag_A_t<T>(sy_of(cyp[u])) * (dX - w[4]))) +
+                             (inv_diag_A_t<T>(sz_of(cX[u])) * (dX - w[5]) +
+                              inv_diag_A_t<T>(sz_of(czp[u])) * (dX - w[6]));
+                acc[0] += in ? (double)dX * (double)qv : 0.0;
                 if (in) q[nb[u].X] = qv;
             }
         }
@@ -724,17 +749,18 @@ __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const d
     write_partials<1>(acc, part, kDQ, c.lb);
 }
 
-__global__ void k_cgS_update(Sweep s, const double* __restrict__ invd, double* __restrict__ x, double* __restrict__ r,
-                             const double* __restrict__ d, const double* __restrict__ q, CgState* st, double* part,
-                             int j) {
+template <class T>
+__global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict__ x, T* __restrict__ r,
+                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part, int j) {
     if (st->done) return;
-    double alpha;
-    if (cg_update_scalars(st, part, s.nblk, j, &alpha)) return;
+    double alpha_d;
+    if (cg_update_scalars(st, part, s.nblk, j, &alpha_d)) return;
+    const T alpha = (T)alpha_d;
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
         for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
-            double xv[kZBatch], rv[kZBatch], dv[kZBatch], qv[kZBatch], iv[kZBatch];
+            T xv[kZBatch], rv[kZBatch], dv[kZBatch], qv[kZBatch], iv[kZBatch];
 #pragma unroll
             for (int u = 0; u < kZBatch; ++u) {
                 const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
@@ -747,11 +773,11 @@ __global__ void k_cgS_update(Sweep s, const double* __restrict__ invd, double* _
 #pragma unroll
             for (int u = 0; u < kZBatch; ++u) {
                 const bool in = k0 + u < c.k1;
-                const double xn = xv[u] + alpha * dv[u];
-                const double rn = rv[u] - alpha * qv[u];
-                const double z = rn * iv[u];
-                acc[0] += in ? rn * z : 0.0;
-                acc[1] += in ? z * z : 0.0;
+                const T xn = xv[u] + alpha * dv[u];
+                const T rn = rv[u] - alpha * qv[u];
+                const T z = rn * iv[u];
+                acc[0] += in ? (double)rn * (double)z : 0.0;
+                acc[1] += in ? (double)z * (double)z : 0.0;
                 if (in) {
                     const int X = c.X0 + (k0 + u) * s.N2;
                     x[X] = xn;
@@ -761,6 +787,77 @@ __global__ void k_cgS_update(Sweep s, const double* __restrict__ invd, double* _
         }
     }
     write_partials<2>(acc, part, kRZ, c.lb);
+}
+
+// ---- mixed-precision helpers -------------------------------------------------
+// out = in converted to FP64 (cells)
+__global__ void k_widen_cells(Sweep s, const float* __restrict__ in, double* __restrict__ out) {
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        out[X] = (double)in[X];
+    }
+}
+
+__global__ void k_narrow_cells(Sweep s, const double* __restrict__ in, float* __restrict__ out) {
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        out[X] = (float)in[X];
+    }
+}
+
+// res = rhs - A u in FP64 on active faces (residual of the velocity refinement);
+// partials of (res, res) and (rhs, rhs) to out[3*b + 0..1]
+__global__ void k_residual_A(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ rhs,
+                             const double* __restrict__ u, double* __restrict__ res, double* __restrict__ out) {
+    const Column c = sweep_column(s);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (c.valid) {
+        for (int k = c.k0; k < c.k1; ++k) {
+            const Nbr n = neighbours(s, c, k);
+            const int cd = code[n.X];
+            const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const size_t off = (size_t)a * s.n3;
+                const double bv = rhs[off + n.X];
+                const double v = sc[a] ? bv - apply_A_face(u + off, n, sc[a]) : 0.0;
+                res[off + n.X] = v;
+                acc[0] += v * v;
+                acc[1] += sc[a] ? bv * bv : 0.0;
+            }
+        }
+    }
+    block_sum_all<3>(acc);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[3 * c.lb + q] = acc[q];
+}
+
+// u += a v with v in FP32 (faces)
+__global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* __restrict__ v, double a) {
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        for (int q = 0; q < 3; ++q) u[(size_t)q * s.n3 + X] += a * (double)v[(size_t)q * s.n3 + X];
+    }
+}
+
+// (B v)_X with v in FP32, result in FP64
+__global__ void k_apply_B_f32(Sweep s, const float* __restrict__ u, double* __restrict__ out) {
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    const float* ux = u;
+    const float* uy = u + (size_t)s.n3;
+    const float* uz = u + 2 * (size_t)s.n3;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const Nbr n = neighbours(s, c, k);
+        out[n.X] = (((double)ux[n.X] - (double)ux[n.xp]) + ((double)uy[n.X] - (double)uy[n.yp])) +
+                   ((double)uz[n.X] - (double)uz[n.zp]);
+    }
 }
 
 // ---------------------------------------------------------------------------

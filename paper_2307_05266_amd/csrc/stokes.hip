@@ -81,6 +81,10 @@ struct stokes_ctx {
     double *p = nullptr, *r = nullptr, *zs = nullptr, *d = nullptr, *q = nullptr;  // cells
     double *sr = nullptr, *sq = nullptr, *invdS = nullptr;                         // cells (SIMPLE solve)
     double* sd = nullptr;                                                          // cells, inner direction
+    // FP32 inner-solve vectors of the mixed-precision path (allocated on first use)
+    float *fx32 = nullptr, *fr32 = nullptr, *fd32 = nullptr, *fq32 = nullptr;     // faces
+    float *zs32 = nullptr, *sr32 = nullptr, *sd32 = nullptr, *sq32 = nullptr;     // cells
+    float* invdS32 = nullptr;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -89,6 +93,13 @@ struct stokes_ctx {
     CgState* host_state = nullptr; // pinned
     double* host_part = nullptr;   // pinned [3 * kMaxBlocks]
     int sweep_blocks = 1024;
+    // mixed precision: FP32 inner solves, FP64 outer flexible CG with FP64
+    // true-residual refinement
+    int precision = 0;             // 0: FP64 throughout, 1: mixed
+    double eps_A32 = 1e-5, eps_S32 = 1e-5;   // FP32 inner tolerances
+    double cycle_rtol = 1e-4;      // residual reduction per defect-correction cycle
+    double eps_refine = 1e-12;     // FP64 velocity refinement tolerance
+    int max_refine = 12;
 
     // options
     double eps_A = 1e-12, eps_S = 1e-12;
@@ -212,14 +223,31 @@ int first_batch(stokes_ctx* c, int which) {
 
 int next_batch(stokes_ctx* c) { return c->check_every > 0 ? c->check_every : 4; }
 
-// Solve A x = b on the faces (b == nullptr: the uniform force).  x -> c->fx.
-// Iteration j launches the dir, stencil and update kernels; the host polls the
-// device state between batches.
-stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+// Inner solves in the value type T (double, or float on the mixed path).
+template <class T>
+struct InnerA {
+    T *x, *r, *d, *q;
+};
+template <class T>
+struct InnerS {
+    T *x, *r, *d, *q;
+    const T* invd;
+};
+
+InnerA<double> bufA64(stokes_ctx* c) { return {c->fx, c->fr, c->fd, c->fq}; }
+InnerA<float> bufA32(stokes_ctx* c) { return {c->fx32, c->fr32, c->fd32, c->fq32}; }
+InnerS<double> bufS64(stokes_ctx* c) { return {c->zs, c->sr, c->sd, c->sq, c->invdS}; }
+InnerS<float> bufS32(stokes_ctx* c) { return {c->zs32, c->sr32, c->sd32, c->sq32, c->invdS32}; }
+
+// Solve A x = b on the faces (b: an FP64 face vector, or nullptr for the
+// uniform force).  Iteration j launches the dir, stencil and update kernels;
+// the host polls the device state between batches.
+template <class T>
+stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
     CgState* st = c->cg + 0;
-    hipLaunchKernelGGL(k_cgA_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0], c->force[1],
-                       c->force[2], c->fx, c->fr, st, c->part, eps, c->max_inner);
+    hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
+                       c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     int batch = first_batch(c, 0);
     int j = 0;
@@ -228,16 +256,16 @@ stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* 
         for (int t = 0; t < batch; ++t, ++j) {
             bool open;
             ST_TRY(time_begin(c, kTimeADir, &open));
-            hipLaunchKernelGGL(k_cgA_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->fd, st,
+            hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st,
                                c->part, j);
             ST_TRY(time_end(c, open));
             ST_TRY(time_begin(c, kTimeAStencil, &open));
-            hipLaunchKernelGGL(k_cgA_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fd, c->fq, st,
+            hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                                c->part);
             ST_TRY(time_end(c, open));
             ST_TRY(time_begin(c, kTimeAUpdate, &open));
-            hipLaunchKernelGGL(k_cgA_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fx, c->fr, c->fd,
-                               c->fq, st, c->part, j);
+            hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d,
+                               v.q, st, c->part, j);
             ST_TRY(time_end(c, open));
         }
         HIP_TRY(hipGetLastError());
@@ -251,11 +279,16 @@ stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* 
     return STOKES_OK;
 }
 
-// Solve Shat x = b on the cells (b already projected).  x -> c->zs.
-stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    return cg_A<double>(c, bufA64(c), b, eps, iters, status);
+}
+
+// Solve Shat x = b on the cells (b: an FP64 cell vector, already projected).
+template <class T>
+stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
     CgState* st = c->cg + 1;
-    hipLaunchKernelGGL(k_cgS_init, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, b, c->zs, c->sr, st, c->part,
+    hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     int batch = first_batch(c, 1);
@@ -265,16 +298,16 @@ stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* 
         for (int t = 0; t < batch; ++t, ++j) {
             bool open;
             ST_TRY(time_begin(c, kTimeSDir, &open));
-            hipLaunchKernelGGL(k_cgS_dir, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, c->sr, c->sd, st,
+            hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st,
                                c->part, j);
             ST_TRY(time_end(c, open));
             ST_TRY(time_begin(c, kTimeSStencil, &open));
-            hipLaunchKernelGGL(k_cgS_stencil, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->sd, c->sq, st,
+            hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                                c->part);
             ST_TRY(time_end(c, open));
             ST_TRY(time_begin(c, kTimeSUpdate, &open));
-            hipLaunchKernelGGL(k_cgS_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->invdS, c->zs, c->sr, c->sd,
-                               c->sq, st, c->part, j);
+            hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d,
+                               v.q, st, c->part, j);
             ST_TRY(time_end(c, open));
         }
         HIP_TRY(hipGetLastError());
@@ -286,6 +319,10 @@ stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* 
     *iters = h.it;
     *status = h.status;
     return STOKES_OK;
+}
+
+stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    return cg_S<double>(c, bufS64(c), b, eps, iters, status);
 }
 
 // ---- outer-loop helpers ---------------------------------------------------------
@@ -553,6 +590,22 @@ stokes_status stokes_set_stream(stokes_ctx* c, void* stream) {
     return STOKES_OK;
 }
 
+// FP32 vectors of the mixed-precision path, allocated on first use.
+static stokes_status ensure_mixed_buffers(stokes_ctx* c) {
+    if (c->fx32) return STOKES_OK;
+    const int64_t n3 = c->n3;
+    for (float** f : {&c->fx32, &c->fr32, &c->fd32, &c->fq32}) ST_TRY(dev_alloc(c, f, (size_t)(3 * n3)));
+    for (float** v : {&c->zs32, &c->sr32, &c->sd32, &c->sq32, &c->invdS32}) ST_TRY(dev_alloc(c, v, (size_t)n3));
+    for (float* f : {c->fx32, c->fr32, c->fd32, c->fq32})
+        HIP_TRY(hipMemsetAsync(f, 0, (size_t)(3 * n3) * sizeof(float), c->stream));
+    for (float* v : {c->zs32, c->sr32, c->sd32, c->sq32})
+        HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(float), c->stream));
+    hipLaunchKernelGGL(k_narrow_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->invdS, c->invdS32);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return STOKES_OK;
+}
+
 stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     if (!c || !key || !std::isfinite(v)) return STOKES_E_ARG;
     const std::string k(key);
@@ -567,6 +620,15 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         c->timing = (int)v;
     }
     else if (k == "true_velocity") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->true_velocity = (int)v; }
+    else if (k == "precision") {
+        if (v != 0.0 && v != 1.0) return STOKES_E_ARG;
+        if (v == 1.0) ST_TRY(ensure_mixed_buffers(c));
+        c->precision = (int)v;
+    }
+    else if (k == "eps_A32") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_A32 = v; }
+    else if (k == "eps_S32") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_S32 = v; }
+    else if (k == "cycle_rtol") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->cycle_rtol = v; }
+    else if (k == "eps_refine") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_refine = v; }
     else if (k == "sweep_blocks") {
         if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
         const Sweep sw = make_sweep(c->N, (int)v);
@@ -577,6 +639,8 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else return STOKES_E_ARG;
     return STOKES_OK;
 }
+
+static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double tol);
 
 static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double tol) {
     stokes_report& R = c->rep;
@@ -602,6 +666,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
         c->have_solution = true;
         return STOKES_OK;
     }
+    if (c->precision == 1) return solve_mixed(c, precond, tol);
 
     int itA = 0, itS = 0, stA = 0, stS = 0;
     int64_t totA = 0, totS = 0;
@@ -728,6 +793,185 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
     R.rel_res = rel;
     R.rel_res_prec = relz;
     if (!alphas.empty()) {
+        betas.resize(alphas.size() - 1 < betas.size() ? alphas.size() - 1 : betas.size());
+        lanczos_extremes(alphas, betas, &R.ritz_min, &R.ritz_max);
+        R.cond_est = R.ritz_max / R.ritz_min;
+    }
+    R.status = status;
+    ST_TRY(collect_timing(c));
+    c->have_solution = status >= 0;
+    return (stokes_status)status;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: FP32 inner solves, FP64 outer recurrences.
+//
+// Defect correction around a flexible outer CG.  Each cycle starts from the
+// true residual r = g - S p = B u, u = A^{-1}(f - B^T p) held in FP64 and
+// refined to eps_refine (FP32 CG sweeps on FP64 residuals); inside a cycle the
+// outer CG (flexible beta = (z_k+1, r_k+1 - r_k) / (z_k, r_k), Notay's FCG,
+// which tolerates the inexact FP32 preconditioner and S) reduces the recursive
+// residual by cycle_rtol, updating p and the recursive velocity; the cycle ends
+// with the refinement of u and a fresh true residual.  The solve stops when the
+// true residual meets tol.
+// ---------------------------------------------------------------------------
+// u <- A^{-1}(f - B^T p) to eps_refine, starting from the current u.
+static stokes_status refine_velocity(stokes_ctx* c, int64_t* totA, int* inner_status) {
+    const Sweep& s = c->sw;
+    hipLaunchKernelGGL(k_force_minus_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->p, c->force[0],
+                       c->force[1], c->force[2], c->fr);
+    HIP_TRY(hipGetLastError());
+    for (int round = 0;; ++round) {
+        hipLaunchKernelGGL(k_residual_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->u, c->fq,
+                           c->dpart);
+        HIP_TRY(hipGetLastError());
+        double t[3];
+        ST_TRY(host_totals(c, t));
+        const double rel = t[1] > 0.0 ? std::sqrt(t[0] / t[1]) : 0.0;
+        if (!std::isfinite(rel)) return STOKES_E_BREAKDOWN;
+        if (rel < c->eps_refine || round >= c->max_refine) break;
+        int it = 0, st = 0;
+        ST_TRY(cg_A<float>(c, bufA32(c), c->fq, c->eps_A32, &it, &st));
+        *totA += it;
+        if (st == -4) *inner_status = -4;
+        hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx32, 1.0);
+        HIP_TRY(hipGetLastError());
+    }
+    return STOKES_OK;
+}
+
+// z <- SIMPLE^+ r in FP32 (widened and projected), or z = r for Uzawa
+static stokes_status mixed_precond(stokes_ctx* c, stokes_precond precond, int64_t* totS, int* inner_status) {
+    if (precond == STOKES_UZAWA) {
+        HIP_TRY(hipMemcpyAsync(c->zs, c->r, (size_t)c->n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        return STOKES_OK;
+    }
+    int it = 0, st = 0;
+    ST_TRY(cg_S<float>(c, bufS32(c), c->r, c->eps_S32, &it, &st));
+    *totS += it;
+    if (st == -4) *inner_status = -4;
+    hipLaunchKernelGGL(k_widen_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->zs32, c->zs);
+    HIP_TRY(hipGetLastError());
+    return project(c, c->zs);
+}
+
+static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double tol) {
+    stokes_report& R = c->rep;
+    const Sweep& s = c->sw;
+    const int64_t n3 = c->n3;
+    const double N2 = (double)c->N * (double)c->N;
+    ST_TRY(ensure_mixed_buffers(c));
+    double* z = c->zs;        // FP64 preconditioned residual
+    double* r_old = c->sr;    // FP64 previous residual (flexible beta)
+    int64_t totA = 0, totS = 0;
+    int inner_status = 0, status = STOKES_OK;
+    HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+    ST_TRY(refine_velocity(c, &totA, &inner_status));
+    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
+    HIP_TRY(hipGetLastError());
+    ST_TRY(project(c, c->r));
+    double dd[3];
+    ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd));
+    const double r0 = std::sqrt(dd[0]);
+    R.r0_norm = r0;
+    double rel = 0.0, relz = 0.0, z0 = 0.0;
+    int k = 0;
+    int cycle = 0;
+    std::vector<double> alphas, betas;   // first cycle only: a restart starts a new Krylov space
+    if (!(r0 > 0.0)) {
+        R.flags |= STOKES_FLAG_ZERO_RHS;
+    } else {
+        bool done = false;
+        for (; !done && status >= 0; ++cycle) {
+            // one defect-correction cycle on the current true residual
+            ST_TRY(mixed_precond(c, precond, &totS, &inner_status));
+            ST_TRY(dots(c, c->r, z, c->r, c->r, z, z, dd));
+            double rz = dd[0];
+            const double rs = std::sqrt(dd[1]);
+            if (z0 == 0.0) z0 = std::sqrt(dd[2]);
+            const double target = std::max(tol * r0, c->cycle_rtol * rs);
+            HIP_TRY(hipMemcpyAsync(c->d, z, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            for (;;) {
+                if (k >= c->max_outer) { status = STOKES_NOT_CONVERGED; break; }
+                const int64_t a0 = totA, s0 = totS;
+                hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->d, c->fr);
+                HIP_TRY(hipGetLastError());
+                int it = 0, st = 0;
+                ST_TRY(cg_A<float>(c, bufA32(c), c->fr, c->eps_A32, &it, &st));
+                totA += it;
+                if (st == -4) inner_status = -4;
+                hipLaunchKernelGGL(k_apply_B_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx32, c->q);
+                HIP_TRY(hipGetLastError());
+                ST_TRY(dots(c, c->d, c->q, nullptr, nullptr, nullptr, nullptr, dd));
+                const double dq = dd[0];
+                if (!(dq > 0.0) || !std::isfinite(dq)) { status = STOKES_E_BREAKDOWN; break; }
+                const double alpha = rz / dq;
+                HIP_TRY(hipMemcpyAsync(r_old, c->r, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                hipLaunchKernelGGL(k_outer_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->p, c->r, c->d, c->q,
+                                   alpha);
+                hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx32, -alpha);
+                HIP_TRY(hipGetLastError());
+                ST_TRY(project(c, c->r));
+                ST_TRY(mixed_precond(c, precond, &totS, &inner_status));
+                ++k;
+                ST_TRY(dots(c, z, c->r, z, r_old, c->r, c->r, dd));
+                const double rn = std::sqrt(dd[2]);
+                double zz[3];
+                ST_TRY(dots(c, z, z, nullptr, nullptr, nullptr, nullptr, zz));
+                rel = rn / r0;
+                relz = std::sqrt(zz[0]) / z0;
+                if (!std::isfinite(rel)) { status = STOKES_E_BREAKDOWN; break; }
+                const bool stop = rn <= target;
+                double beta = 0.0;
+                if (!stop) {
+                    beta = (dd[0] - dd[1]) / rz;   // flexible (Notay) beta
+                    rz = dd[0];
+                    hipLaunchKernelGGL(k_dir_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->d, z, beta);
+                    HIP_TRY(hipGetLastError());
+                }
+                if (cycle == 0) {
+                    alphas.push_back(alpha);
+                    if (!stop) betas.push_back(beta);
+                }
+                double sums[3], mean[3];
+                ST_TRY(face_sums(c, c->u, sums));
+                const double kk = kvox_of(c, sums, mean) / N2;
+                c->hist.insert(c->hist.end(),
+                               {rel, relz, kk, (double)(totA - a0), (double)(totS - s0), alpha, beta, 0.0});
+                if (stop) break;
+            }
+            if (status < 0 || status == STOKES_NOT_CONVERGED) break;
+            // the true residual of the new pressure
+            ST_TRY(refine_velocity(c, &totA, &inner_status));
+            hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
+            HIP_TRY(hipGetLastError());
+            ST_TRY(project(c, c->r));
+            ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd));
+            rel = std::sqrt(dd[0]) / r0;
+            if (!c->hist.empty()) c->hist[c->hist.size() - 8] = rel;   // the cycle's last entry: true residual
+            if (rel < tol) done = true;
+        }
+    }
+    ST_TRY(project(c, c->p));
+    if (status >= 0 && inner_status == -4) status = STOKES_E_BREAKDOWN;
+
+    double sums[3], mean[3];
+    ST_TRY(face_sums(c, c->u, sums));
+    R.k_vox = kvox_of(c, sums, mean);
+    R.k_hat = R.k_vox / N2;
+    for (int a = 0; a < 3; ++a) R.mean_u[a] = mean[a];
+    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->q);
+    HIP_TRY(hipGetLastError());
+    double dv[3];
+    ST_TRY(dots(c, c->q, c->q, nullptr, nullptr, nullptr, nullptr, dv));
+    R.div_norm = std::sqrt(dv[0]);
+    R.outer_iters = k;
+    R.inner_A_iters = (int)totA;
+    R.inner_S_iters = (int)totS;
+    R.rel_res = rel;
+    R.rel_res_prec = relz;
+    if (!alphas.empty()) {
+        betas.resize(alphas.size() - 1 < betas.size() ? alphas.size() - 1 : betas.size());
         lanczos_extremes(alphas, betas, &R.ritz_min, &R.ritz_max);
         R.cond_est = R.ritz_max / R.ritz_min;
     }

@@ -1,0 +1,129 @@
+"""GPU parity of the mixed-precision path (FP32 inner solves, FP64 outer flexible
+CG with FP64 velocity refinement) against the FP64 CPU oracle.
+
+The bar for mixed precision is a permeability within 1e-4 relative of the FP64
+oracle; the true FP64 residual ||B u|| / ||g|| must meet the outer tolerance,
+because every defect-correction cycle ends on a velocity refined in FP64.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import grf, slits, spheres
+from synth.geometry import channel_widths
+
+pytestmark = pytest.mark.gpu
+
+K_TOL_MIXED = 1e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_05266_amd as P
+    P.load()
+    return P
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mixed_vs_oracle(P, m, force, pc, tol=1e-8):
+    o = oracle.Oracle(m, force)
+    ref = o.solve(pc, tol=tol)
+    with P.Stokes(m, force, precision=1) as s:
+        rep = s.solve(pc, tol)
+        p, u = s.fields()
+    err = abs(rep["k_hat"] - ref["k_hat"]) / abs(ref["k_hat"]) if ref["k_hat"] else abs(rep["k_hat"])
+    say(f"    mixed k={rep['k_hat']:.14e} oracle={ref['k_hat']:.14e} rel={err:.2e} outer {rep['outer_iters']}/"
+        f"{ref['outer_iters']} div={rep['div_norm']:.2e} r0={rep['r0_norm']:.2e}")
+    assert rep["status"] == 0, rep
+    assert err <= K_TOL_MIXED
+    if rep["outer_iters"] > 0:
+        # the returned velocity is the FP64-refined one: its divergence is the true residual
+        assert rep["div_norm"] <= 1.01 * tol * rep["r0_norm"]
+        assert rep["rel_res"] < tol
+    return rep, ref, p, u, o
+
+
+@pytest.mark.parametrize("pc", ["uzawa", "simple"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mixed_spheres_24(P, pc, seed):
+    say(f"[mixed] spheres 24^3 r=4 phi=0.7 seed={seed} {pc}")
+    pcid = P.STOKES_SIMPLE if pc == "simple" else P.STOKES_UZAWA
+    rep, ref, p, u, o = mixed_vs_oracle(P, spheres(24, 4.0, 0.7, seed), (1.0, 0.0, 0.0), pcid)
+    assert np.abs(u - ref["u"]).max() <= 1e-5 * np.abs(ref["u"]).max()
+
+
+@pytest.mark.parametrize("pc", ["uzawa", "simple"])
+def test_mixed_tight_ragged(P, pc):
+    say(f"[mixed] spheres 37^3 r=2 phi=0.3 {pc}")
+    pcid = P.STOKES_SIMPLE if pc == "simple" else P.STOKES_UZAWA
+    mixed_vs_oracle(P, spheres(37, 2.0, 0.3, 4), (1.0, 0.0, 0.0), pcid)
+
+
+def test_mixed_grf_oblique_multicomponent(P):
+    say("[mixed] grf 40^3 oblique")
+    mixed_vs_oracle(P, grf(40, 3.0, 0.3, 5), (0.3, 0.0, 1.0), P.STOKES_SIMPLE)
+
+
+def test_mixed_slit_closed_form(P):
+    N = 36
+    m = slits(N, [4, 7], axis=1)
+    with P.Stokes(m, (1.0, 0.0, 0.0), precision=1) as s:
+        rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+    ws = channel_widths(N, [4, 7])
+    assert rep["outer_iters"] == 0
+    assert rep["k_vox"] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-10)
+
+
+def test_mixed_oblique_slits(P):
+    N = 48
+    m = slits(N, [3, 4, 6], axis=1)
+    with P.Stokes(m, (1.0, 0.5, 0.0), precision=1) as s:
+        rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+    ws = channel_widths(N, [3, 4, 6])
+    assert rep["mean_u"][0] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-8)
+    assert abs(rep["mean_u"][1]) < 1e-9
+
+
+def test_mixed_matches_fp64_gpu(P):
+    """Same geometry, both paths on the GPU: permeabilities agree far below the
+    mixed-precision bar, and the outer counts stay close."""
+    m = spheres(48, 3.0, 0.45, 9)
+    with P.Stokes(m) as s:
+        a = s.solve(P.STOKES_SIMPLE, 1e-8)
+        s.set_option("precision", 1)
+        b = s.solve(P.STOKES_SIMPLE, 1e-8)
+    say(f"    fp64 k={a['k_hat']:.14e} outer={a['outer_iters']}  mixed k={b['k_hat']:.14e} outer={b['outer_iters']}")
+    assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
+    assert b["outer_iters"] <= 2 * a["outer_iters"] + 5
+
+
+def test_mixed_full_size_equations(P):
+    """128^3 spheres r=6 porosity 0.5 in mixed precision: the discrete equations hold
+    (checked with the oracle's operators) and k matches the FP64 GPU solve."""
+    N = 128
+    m = spheres(N, 6.0, 0.5, 0)
+    say("[mixed full size] spheres 128^3")
+    with P.Stokes(m, precision=1) as s:
+        rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+        p, u = s.fields()
+    say(f"    k={rep['k_hat']:.12e} outer={rep['outer_iters']} innerA={rep['inner_A_iters']} "
+        f"innerS={rep['inner_S_iters']} t={rep['seconds']:.2f}s")
+    assert rep["status"] == 0
+    o = oracle.Oracle(m)
+    Au = o.apply(oracle.OP_A, u)
+    BTp = o.apply(oracle.OP_BT, p)
+    dA = o.apply(oracle.OP_DIAG_A, None)
+    f = np.zeros_like(dA)
+    f[0] = (dA[0] > 0).astype(np.float64)
+    assert np.linalg.norm(Au + BTp - f) <= 1e-8 * np.linalg.norm(f)
+    Bu = o.apply(oracle.OP_B, u)
+    assert np.linalg.norm(Bu) <= 1.01e-8 * rep["r0_norm"]
