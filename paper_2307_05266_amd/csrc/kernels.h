@@ -678,9 +678,11 @@ __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b,
     }
 }
 
+// zpre == nullptr: Jacobi, z = D^-1 r; otherwise z is read from zpre (the
+// multigrid-preconditioned residual)
 template <class T>
 __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restrict__ r, T* __restrict__ d,
-                          CgState* st, double* part, int j) {
+                          CgState* st, double* part, int j, const T* __restrict__ zpre) {
     if (st->done) return;
     double beta_d;
     if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
@@ -693,8 +695,13 @@ __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restri
 #pragma unroll
         for (int u = 0; u < kZBatch; ++u) {
             const int X = c.X0 + (k0 + u < c.k1 ? k0 + u : c.k0) * s.N2;
-            rv[u] = r[X];
-            iv[u] = invd[X];
+            if (zpre) {
+                rv[u] = zpre[X];
+                iv[u] = T(1);
+            } else {
+                rv[u] = r[X];
+                iv[u] = invd[X];
+            }
             dv[u] = d[X];
         }
 #pragma unroll

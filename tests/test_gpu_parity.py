@@ -335,3 +335,20 @@ def test_full_size_solution_satisfies_equations(P, pc):
     fl, comp = o.masks()
     for c in range(o.ncomp_kept):
         assert abs(p[comp == c].mean()) < 1e-10 * max(np.abs(p).max(), 1.0)
+
+
+@pytest.mark.parametrize("N,seed", [(24, 3), (48, 5)])
+def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
+    """The SIMPLE inner solve with the multigrid preconditioner (default) and with
+    Jacobi reach the same outer trajectory: same outer count (+-1), same k."""
+    m = spheres(N, 3.0, 0.45, seed)
+    with P.Stokes(m) as s:
+        s.set_option("mg", 0)
+        a = s.solve(P.STOKES_SIMPLE, 1e-8)
+        s.set_option("mg", 1)
+        b = s.solve(P.STOKES_SIMPLE, 1e-8)
+    say(f"    jacobi: outer={a['outer_iters']} innerS={a['inner_S_iters']}  mg: outer={b['outer_iters']} "
+        f"innerS={b['inner_S_iters']}")
+    assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
+    assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
+    assert b["inner_S_iters"] < a["inner_S_iters"]
