@@ -154,6 +154,12 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 HIP events (0 = off, the default)
  *   "true_velocity" 1: after the solve, recompute u = A^{-1}(f - B^T p)
  *   "sweep_blocks" number of workgroups a sweep aims for (default 1024)
+ *   "mg", "mg_A"  1 (default): precondition the inner CG with the SIMPLE matrix
+ *                 (resp. with A) by a geometric multigrid V-cycle, the role the
+ *                 paper gives to algebraic multigrid (Sec. 3.2); 0: Jacobi.
+ *                 The inner stopping test is the same either way.
+ *   "mg_omega", "mg_scale", "mg_coarse_sweeps"  V-cycle smoothing weight
+ *                 (0.8), coarse-correction scale (1.0), coarsest-level sweeps (16)
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

@@ -512,9 +512,11 @@ __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const doub
 // plane a's face state from a voxel's code
 __device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(code) : (a == 1 ? sy_of(code) : sz_of(code)); }
 
+// zpre == nullptr: Jacobi, z = D^-1 r; otherwise z is read from zpre (the
+// multigrid-preconditioned residual, three planes)
 template <class T>
 __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ r, T* __restrict__ d,
-                          CgState* st, double* part, int j) {
+                          CgState* st, double* part, int j, const T* __restrict__ zpre) {
     if (st->done) return;
     double beta_d;
     if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
@@ -533,7 +535,7 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __
             cd[u] = code[X];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                rv[u][a] = r[(size_t)a * s.n3 + X];
+                rv[u][a] = zpre ? zpre[(size_t)a * s.n3 + X] : r[(size_t)a * s.n3 + X];
                 dv[u][a] = d[(size_t)a * s.n3 + X];
             }
         }
@@ -545,7 +547,7 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __
             T dn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const T z = rv[u][a] * inv_diag_A_t<T>(sc[a]);
+                const T z = zpre ? rv[u][a] : rv[u][a] * inv_diag_A_t<T>(sc[a]);
                 dn[a] = first ? z : z + beta * dv[u][a];
             }
             if (in)

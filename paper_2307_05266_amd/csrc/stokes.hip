@@ -86,16 +86,21 @@ struct stokes_ctx {
     float *fx32 = nullptr, *fr32 = nullptr, *fd32 = nullptr, *fq32 = nullptr;     // faces
     float *zs32 = nullptr, *sr32 = nullptr, *sd32 = nullptr, *sq32 = nullptr;     // cells
     float* invdS32 = nullptr;
-    // multigrid hierarchy of the SIMPLE matrix (levels 1..mg_levels), FP64 and FP32
-    int mg_levels = 0;                 // 0: no hierarchy (odd size or tiny box)
-    std::vector<MgGrid> mg_grid;       // [0..mg_levels]
-    struct MgLev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y; };
-    struct MgLev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y; };
-    std::vector<MgLev64> mg64;         // [1..mg_levels] (entry 0 unused)
-    std::vector<MgLev32> mg32;
-    double *mg_x0 = nullptr, *mg_z = nullptr;   // fine-level presmoothed iterate, output z
-    float *mg_x0_32 = nullptr, *mg_z32 = nullptr;
+    // multigrid hierarchies: the SIMPLE matrix (one plane) and A (three planes)
+    struct MgHier {
+        int levels = 0;                // 0: none (odd size or tiny box)
+        int nb = 1, kind = 0;
+        std::vector<MgGrid> grid;      // [0..levels]
+        struct Lev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y; };
+        struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y; };
+        std::vector<Lev64> l64;        // [1..levels]
+        std::vector<Lev32> l32;
+        double *x0 = nullptr, *z = nullptr;   // fine level: presmoothed iterate, output
+        float *x0_32 = nullptr, *z32 = nullptr;
+    };
+    MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
+    int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
     double mg_omega = 0.8, mg_scale = 1.0;
     int mg_coarse_sweeps = 16;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
@@ -270,7 +275,7 @@ stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int*
             bool open;
             ST_TRY(time_begin(c, kTimeADir, &open));
             hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st,
-                               c->part, j);
+                               c->part, j, (const T*)nullptr);
             ST_TRY(time_end(c, open));
             ST_TRY(time_begin(c, kTimeAStencil, &open));
             hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
@@ -334,72 +339,72 @@ stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int*
     return STOKES_OK;
 }
 
-stokes_status cg_S_mg_double(stokes_ctx* c, const double* b, double eps, int* iters, int* status);
-
 stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
-    if (c->use_mg && c->mg_levels > 0) return cg_S_mg_double(c, b, eps, iters, status);
     return cg_S<double>(c, bufS64(c), b, eps, iters, status);
 }
 
-// ---- multigrid for the SIMPLE matrix -------------------------------------
+// ---- multigrid preconditioners ---------------------------------------------
 int flat_blocks(int n, int cap = 2048) { return std::max(1, std::min(cap, (n + kBlock - 1) / kBlock)); }
+using MgHier = stokes_ctx::MgHier;
 
-// Levels: halve while the side is even and the level holds more than 512
-// nodes; the coarsest level must fit one workgroup's LDS.
-stokes_status build_mg(stokes_ctx* c) {
-    c->mg_levels = 0;
-    c->mg_grid.clear();
+// Levels: halve while the side is even and a level holds more than 512 nodes
+// per plane; the coarsest level must fit one workgroup's LDS.
+stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
+    h.levels = 0;
+    h.nb = nb;
+    h.kind = kind;
+    h.grid.clear();
     int n = c->N;
-    c->mg_grid.push_back({n, n * n, n * n * n});
+    h.grid.push_back({n, n * n, n * n * n, nb});
     while (n % 2 == 0 && n / 2 >= 2 && n * n * n > 512) {
         n /= 2;
-        c->mg_grid.push_back({n, n * n, n * n * n});
+        h.grid.push_back({n, n * n, n * n * n, nb});
     }
-    const int L = (int)c->mg_grid.size() - 1;
-    if (L < 1 || c->mg_grid[L].n3 > kMgCoarsestMax) {
-        c->mg_grid.resize(1);
+    const int L = (int)h.grid.size() - 1;
+    if (L < 1 || nb * h.grid[L].n3 > kMgCoarsestMax) {
+        h.grid.resize(1);
         return STOKES_OK;
     }
-    c->mg64.assign(L + 1, {});
+    h.l64.assign(L + 1, {});
     for (int l = 1; l <= L; ++l) {
-        auto& lv = c->mg64[l];
-        const size_t m = (size_t)c->mg_grid[l].n3;
+        auto& lv = h.l64[l];
+        const size_t m = (size_t)nb * h.grid[l].n3;
         for (double** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, m));
     }
-    ST_TRY(dev_alloc(c, &c->mg_x0, (size_t)c->n3));
-    ST_TRY(dev_alloc(c, &c->mg_z, (size_t)c->n3));
-    const auto& g0 = c->mg_grid[0];
-    const auto& g1 = c->mg_grid[1];
-    hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((g1.n3 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, g0,
-                       g1, c->code, c->mg64[1].D, c->mg64[1].Wx, c->mg64[1].Wy, c->mg64[1].Wz);
+    ST_TRY(dev_alloc(c, &h.x0, (size_t)nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.z, (size_t)nb * c->n3));
+    const int m1 = nb * h.grid[1].n3;
+    hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+                       h.grid[0], h.grid[1], kind, c->code, h.l64[1].D, h.l64[1].Wx, h.l64[1].Wy, h.l64[1].Wz);
     for (int l = 1; l < L; ++l) {
-        const auto& f = c->mg64[l];
-        const auto& t = c->mg64[l + 1];
-        hipLaunchKernelGGL(k_mg_coarsen<double>, dim3((c->mg_grid[l + 1].n3 + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           c->stream, c->mg_grid[l], c->mg_grid[l + 1], f.D, f.Wx, f.Wy, f.Wz, t.D, t.Wx, t.Wy, t.Wz);
+        const auto& f = h.l64[l];
+        const auto& t = h.l64[l + 1];
+        const int m = nb * h.grid[l + 1].n3;
+        hipLaunchKernelGGL(k_mg_coarsen<double>, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+                           h.grid[l], h.grid[l + 1], f.D, f.Wx, f.Wy, f.Wz, t.D, t.Wx, t.Wy, t.Wz);
     }
     HIP_TRY(hipGetLastError());
-    c->mg_levels = L;
+    h.levels = L;
     return STOKES_OK;
 }
 
-// FP32 copy of the hierarchy for the mixed path
-stokes_status build_mg32(stokes_ctx* c) {
-    const int L = c->mg_levels;
-    if (L < 1 || !c->mg32.empty()) return STOKES_OK;
-    c->mg32.assign(L + 1, {});
+// FP32 copy of a hierarchy for the mixed path
+stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
+    const int L = h.levels;
+    if (L < 1 || !h.l32.empty()) return STOKES_OK;
+    h.l32.assign(L + 1, {});
     for (int l = 1; l <= L; ++l) {
-        auto& lv = c->mg32[l];
-        const int m = c->mg_grid[l].n3;
+        auto& lv = h.l32[l];
+        const int m = h.nb * h.grid[l].n3;
         for (float** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, (size_t)m));
-        const auto& d = c->mg64[l];
+        const auto& d = h.l64[l];
         const double* src[4] = {d.D, d.Wx, d.Wy, d.Wz};
         float* dst[4] = {lv.D, lv.Wx, lv.Wy, lv.Wz};
         for (int q = 0; q < 4; ++q)
             hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m)), dim3(kBlock), 0, c->stream, m, src[q], dst[q]);
     }
-    ST_TRY(dev_alloc(c, &c->mg_x0_32, (size_t)c->n3));
-    ST_TRY(dev_alloc(c, &c->mg_z32, (size_t)c->n3));
+    ST_TRY(dev_alloc(c, &h.x0_32, (size_t)h.nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -408,67 +413,61 @@ template <class T>
 struct MgView {
     T *D, *Wx, *Wy, *Wz, *b, *x, *y;
 };
-MgView<double> mg_view(stokes_ctx* c, int l, double) {
-    auto& v = c->mg64[l];
+MgView<double> mg_view(MgHier& h, int l, double) {
+    auto& v = h.l64[l];
     return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y};
 }
-MgView<float> mg_view(stokes_ctx* c, int l, float) {
-    auto& v = c->mg32[l];
+MgView<float> mg_view(MgHier& h, int l, float) {
+    auto& v = h.l32[l];
     return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y};
 }
-double* mg_fine_x(stokes_ctx* c, double) { return c->mg_x0; }
-float* mg_fine_x(stokes_ctx* c, float) { return c->mg_x0_32; }
+double* mg_fine_x(MgHier& h, double) { return h.x0; }
+float* mg_fine_x(MgHier& h, float) { return h.x0_32; }
+double* mg_out(MgHier& h, double) { return h.z; }
+float* mg_out(MgHier& h, float) { return h.z32; }
 
 // z0 = V-cycle applied to the fine residual b0; the last fine sweep writes the
 // partials of (b0, z0) into the RZ slot of the CG loop (grid = the CG sweeps').
 template <class T>
-stokes_status vcycle(stokes_ctx* c, const T* b0, const T* invd0, T* z0, const CgState* st) {
-    const int L = c->mg_levels;
+stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st) {
+    const int L = h.levels;
     const T omega = (T)c->mg_omega, scale = (T)c->mg_scale;
     std::vector<MgOp> ops(L + 1);
-    ops[0] = {c->code, invd0, nullptr, nullptr, nullptr, nullptr};
+    ops[0] = {c->code, h.kind, invd0, nullptr, nullptr, nullptr, nullptr};
     for (int l = 1; l <= L; ++l) {
-        auto v = mg_view(c, l, T());
-        ops[l] = {nullptr, nullptr, v.D, v.Wx, v.Wy, v.Wz};
+        auto v = mg_view(h, l, T());
+        ops[l] = {nullptr, 0, nullptr, v.D, v.Wx, v.Wy, v.Wz};
     }
+    auto nodes = [&](int l) { return h.nb * h.grid[l].n3; };
     // descend: presmooth, restrict
     for (int l = 0; l < L; ++l) {
-        const MgGrid& g = c->mg_grid[l];
-        const T* b = l == 0 ? b0 : mg_view(c, l, T()).b;
-        T* x = l == 0 ? mg_fine_x(c, T()) : mg_view(c, l, T()).x;
-        hipLaunchKernelGGL(k_mg_presmooth<T>, dim3(flat_blocks(g.n3)), dim3(kBlock), 0, c->stream, g, ops[l], b, x,
-                           omega, st);
-        hipLaunchKernelGGL(k_mg_restrict<T>, dim3(flat_blocks(c->mg_grid[l + 1].n3)), dim3(kBlock), 0, c->stream, g,
-                           c->mg_grid[l + 1], ops[l], b, (const T*)x, mg_view(c, l + 1, T()).b, st);
+        const T* b = l == 0 ? b0 : mg_view(h, l, T()).b;
+        T* x = l == 0 ? mg_fine_x(h, T()) : mg_view(h, l, T()).x;
+        hipLaunchKernelGGL(k_mg_presmooth<T>, dim3(flat_blocks(nodes(l))), dim3(kBlock), 0, c->stream, h.grid[l],
+                           ops[l], b, x, omega, st);
+        hipLaunchKernelGGL(k_mg_restrict<T>, dim3(flat_blocks(nodes(l + 1))), dim3(kBlock), 0, c->stream, h.grid[l],
+                           h.grid[l + 1], ops[l], b, (const T*)x, mg_view(h, l + 1, T()).b, st);
     }
     // coarsest: Jacobi sweeps in one workgroup, result in x
     {
-        auto v = mg_view(c, L, T());
-        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1), dim3(1024), 0, c->stream, c->mg_grid[L], ops[L],
-                           (const T*)v.b, v.x, omega, c->mg_coarse_sweeps, st);
+        auto v = mg_view(h, L, T());
+        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1), dim3(1024), 0, c->stream, h.grid[L], ops[L], (const T*)v.b,
+                           v.x, omega, c->mg_coarse_sweeps, st);
     }
     // ascend: prolong the correction and postsmooth; the result of level l is
     // in its y (level 0: z0)
     for (int l = L - 1; l >= 0; --l) {
-        const MgGrid& g = c->mg_grid[l];
-        const T* b = l == 0 ? b0 : mg_view(c, l, T()).b;
-        const T* x = l == 0 ? mg_fine_x(c, T()) : mg_view(c, l, T()).x;
-        const T* xc = (l + 1 == L) ? mg_view(c, L, T()).x : mg_view(c, l + 1, T()).y;
-        T* y = l == 0 ? z0 : mg_view(c, l, T()).y;
-        const int grid = l == 0 ? c->sw.nblk : flat_blocks(g.n3);
-        hipLaunchKernelGGL(k_mg_postsmooth<T>, dim3(grid), dim3(kBlock), 0, c->stream, g, ops[l], b, x, xc,
-                           c->mg_grid[l + 1].n, scale, omega, y, l == 0 ? c->part : nullptr, kRZ, st);
+        const T* b = l == 0 ? b0 : mg_view(h, l, T()).b;
+        const T* x = l == 0 ? mg_fine_x(h, T()) : mg_view(h, l, T()).x;
+        const T* xc = (l + 1 == L) ? mg_view(h, L, T()).x : mg_view(h, l + 1, T()).y;
+        T* y = l == 0 ? z0 : mg_view(h, l, T()).y;
+        const int grid = l == 0 ? c->sw.nblk : flat_blocks(nodes(l));
+        hipLaunchKernelGGL(k_mg_postsmooth<T>, dim3(grid), dim3(kBlock), 0, c->stream, h.grid[l], ops[l], b, x, xc,
+                           h.grid[l + 1].n, scale, omega, y, l == 0 ? c->part : nullptr, kRZ, st);
     }
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
-
-template <class T>
-T* mg_z(stokes_ctx* c);
-template <>
-double* mg_z<double>(stokes_ctx* c) { return c->mg_z; }
-template <>
-float* mg_z<float>(stokes_ctx* c) { return c->mg_z32; }
 
 // Multigrid-preconditioned CG with the SIMPLE matrix; the stopping test stays
 // on the Jacobi-scaled residual ||D^-1 r|| / ||D^-1 r_0||.
@@ -476,11 +475,11 @@ template <class T>
 stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
     CgState* st = c->cg + 1;
-    T* z = mg_z<T>(c);
+    T* z = mg_out(c->mgS, T());
     hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
-    ST_TRY(vcycle<T>(c, v.r, v.invd, z, nullptr));
+    ST_TRY(vcycle<T>(c, c->mgS, v.r, v.invd, z, nullptr));
     int batch = first_batch(c, 1);
     int j = 0;
     CgState h{};
@@ -499,7 +498,7 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
             hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d,
                                v.q, st, c->part, j);
             ST_TRY(time_end(c, open));
-            ST_TRY(vcycle<T>(c, v.r, v.invd, z, st));
+            ST_TRY(vcycle<T>(c, c->mgS, v.r, v.invd, z, st));
         }
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(c, 1, &h));
@@ -512,8 +511,66 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
     return STOKES_OK;
 }
 
-stokes_status cg_S_mg_double(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
-    return cg_S_mg<double>(c, bufS64(c), b, eps, iters, status);
+// Multigrid-preconditioned CG with A (three planes); stopping test on the
+// Jacobi-scaled residual as in the plain solve.
+template <class T>
+stokes_status cg_A_mg(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
+    const Sweep& s = c->sw;
+    CgState* st = c->cg + 0;
+    T* z = mg_out(c->mgA, T());
+    hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
+                       c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
+    HIP_TRY(hipGetLastError());
+    ST_TRY(vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, nullptr));
+    int batch = first_batch(c, 0);
+    int j = 0;
+    CgState h{};
+    for (;;) {
+        for (int t = 0; t < batch; ++t, ++j) {
+            bool open;
+            ST_TRY(time_begin(c, kTimeADir, &open));
+            hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st,
+                               c->part, j, (const T*)z);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeAStencil, &open));
+            hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+                               c->part);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeAUpdate, &open));
+            hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d,
+                               v.q, st, c->part, j);
+            ST_TRY(time_end(c, open));
+            ST_TRY(vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, st));
+        }
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(c, 0, &h));
+        if (h.done) break;
+        batch = next_batch(c);
+    }
+    c->last_it[0] = h.it;
+    *iters = h.it;
+    *status = h.status;
+    return STOKES_OK;
+}
+
+// precision-generic dispatch between the multigrid and Jacobi inner solves
+template <class T>
+stokes_status inner_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
+    if (c->use_mg_A && c->mgA.levels > 0) return cg_A_mg<T>(c, v, b, eps, iters, status);
+    return cg_A<T>(c, v, b, eps, iters, status);
+}
+template <class T>
+stokes_status inner_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
+    if (c->use_mg && c->mgS.levels > 0) return cg_S_mg<T>(c, v, b, eps, iters, status);
+    return cg_S<T>(c, v, b, eps, iters, status);
+}
+
+
+stokes_status solve_S64(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    return inner_S<double>(c, bufS64(c), b, eps, iters, status);
+}
+stokes_status solve_A64(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
+    return inner_A<double>(c, bufA64(c), b, eps, iters, status);
 }
 
 // ---- outer-loop helpers ---------------------------------------------------------
@@ -688,7 +745,8 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     hipLaunchKernelGGL(k_face_codes, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->bits, c->wpr, c->code);
     hipLaunchKernelGGL(k_inv_diag_Shat, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->invdS);
     HIP_TRY(hipGetLastError());
-    ST_TRY(build_mg(c));
+    ST_TRY(build_mg(c, c->mgS, 1, kMgFineShat));
+    ST_TRY(build_mg(c, c->mgA, 3, kMgFineA));
     HIP_TRY(hipStreamSynchronize(c->stream));  // the host vectors above go out of scope
 
     // active faces per direction (host count from the remaining fluid)
@@ -794,7 +852,8 @@ static stokes_status ensure_mixed_buffers(stokes_ctx* c) {
         HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(float), c->stream));
     hipLaunchKernelGGL(k_narrow_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->invdS, c->invdS32);
     HIP_TRY(hipGetLastError());
-    ST_TRY(build_mg32(c));
+    ST_TRY(build_mg32(c, c->mgS));
+    ST_TRY(build_mg32(c, c->mgA));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return STOKES_OK;
 }
@@ -823,6 +882,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "cycle_rtol") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->cycle_rtol = v; }
     else if (k == "eps_refine") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_refine = v; }
     else if (k == "mg") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_mg = (int)v; }
+    else if (k == "mg_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_mg_A = (int)v; }
     else if (k == "mg_omega") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->mg_omega = v; }
     else if (k == "mg_scale") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale = v; }
     else if (k == "mg_coarse_sweeps") { if (v < 1 || v > 1000) return STOKES_E_ARG; c->mg_coarse_sweeps = (int)v; }
@@ -874,7 +934,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
     };
 
     // u0 = A^{-1} f
-    ST_TRY(cg_A(c, nullptr, c->eps_A, &itA, &stA));
+    ST_TRY(solve_A64(c, nullptr, c->eps_A, &itA, &stA));
     totA += itA;
     note_inner(stA);
     std::swap(c->u, c->fx);
@@ -884,7 +944,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
     ST_TRY(project(c, c->r));
     double* z = c->r;
     if (precond == STOKES_SIMPLE) {
-        ST_TRY(cg_S(c, c->r, c->eps_S, &itS, &stS));
+        ST_TRY(solve_S64(c, c->r, c->eps_S, &itS, &stS));
         totS += itS;
         note_inner(stS);
         ST_TRY(project(c, c->zs));
@@ -912,7 +972,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
             // q = S d = B A^{-1} B^T d
             hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->d, c->fr);
             HIP_TRY(hipGetLastError());
-            ST_TRY(cg_A(c, c->fr, c->eps_A, &itA, &stA));
+            ST_TRY(solve_A64(c, c->fr, c->eps_A, &itA, &stA));
             totA += itA;
             note_inner(stA);
             hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx, c->q);
@@ -931,7 +991,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
             HIP_TRY(hipGetLastError());
             ST_TRY(project(c, c->r));
             if (precond == STOKES_SIMPLE) {
-                ST_TRY(cg_S(c, c->r, c->eps_S, &itS, &stS));
+                ST_TRY(solve_S64(c, c->r, c->eps_S, &itS, &stS));
                 totS += itS;
                 note_inner(stS);
                 ST_TRY(project(c, c->zs));
@@ -968,7 +1028,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
         hipLaunchKernelGGL(k_force_minus_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->p, c->force[0],
                            c->force[1], c->force[2], c->fr);
         HIP_TRY(hipGetLastError());
-        ST_TRY(cg_A(c, c->fr, c->eps_A, &itA, &stA));
+        ST_TRY(solve_A64(c, c->fr, c->eps_A, &itA, &stA));
         totA += itA;
         note_inner(stA);
         std::swap(c->u, c->fx);
@@ -1028,7 +1088,7 @@ static stokes_status refine_velocity(stokes_ctx* c, int64_t* totA, int* inner_st
         if (!std::isfinite(rel)) return STOKES_E_BREAKDOWN;
         if (rel < c->eps_refine || round >= c->max_refine) break;
         int it = 0, st = 0;
-        ST_TRY(cg_A<float>(c, bufA32(c), c->fq, c->eps_A32, &it, &st));
+        ST_TRY(inner_A<float>(c, bufA32(c), c->fq, c->eps_A32, &it, &st));
         *totA += it;
         if (st == -4) *inner_status = -4;
         hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx32, 1.0);
@@ -1044,8 +1104,7 @@ static stokes_status mixed_precond(stokes_ctx* c, stokes_precond precond, int64_
         return STOKES_OK;
     }
     int it = 0, st = 0;
-    if (c->use_mg && c->mg_levels > 0) ST_TRY(cg_S_mg<float>(c, bufS32(c), c->r, c->eps_S32, &it, &st));
-    else ST_TRY(cg_S<float>(c, bufS32(c), c->r, c->eps_S32, &it, &st));
+    ST_TRY(inner_S<float>(c, bufS32(c), c->r, c->eps_S32, &it, &st));
     *totS += it;
     if (st == -4) *inner_status = -4;
     hipLaunchKernelGGL(k_widen_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->zs32, c->zs);
@@ -1095,7 +1154,7 @@ static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double t
                 hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->d, c->fr);
                 HIP_TRY(hipGetLastError());
                 int it = 0, st = 0;
-                ST_TRY(cg_A<float>(c, bufA32(c), c->fr, c->eps_A32, &it, &st));
+                ST_TRY(inner_A<float>(c, bufA32(c), c->fr, c->eps_A32, &it, &st));
                 totA += it;
                 if (st == -4) inner_status = -4;
                 hipLaunchKernelGGL(k_apply_B_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx32, c->q);
@@ -1259,7 +1318,7 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
     case STOKES_OP_S: {
         hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, c->fr);
         int it = 0, st = 0;
-        ST_TRY(cg_A(c, c->fr, c->eps_A, &it, &st));
+        ST_TRY(solve_A64(c, c->fr, c->eps_A, &it, &st));
         if (st == -4) return STOKES_E_BREAKDOWN;
         hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx, dst);
         break;

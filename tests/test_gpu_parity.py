@@ -344,11 +344,14 @@ def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
     m = spheres(N, 3.0, 0.45, seed)
     with P.Stokes(m) as s:
         s.set_option("mg", 0)
+        s.set_option("mg_A", 0)
         a = s.solve(P.STOKES_SIMPLE, 1e-8)
         s.set_option("mg", 1)
+        s.set_option("mg_A", 1)
         b = s.solve(P.STOKES_SIMPLE, 1e-8)
-    say(f"    jacobi: outer={a['outer_iters']} innerS={a['inner_S_iters']}  mg: outer={b['outer_iters']} "
-        f"innerS={b['inner_S_iters']}")
+    say(f"    jacobi: outer={a['outer_iters']} innerA={a['inner_A_iters']} innerS={a['inner_S_iters']}  "
+        f"mg: outer={b['outer_iters']} innerA={b['inner_A_iters']} innerS={b['inner_S_iters']}")
     assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
     assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
     assert b["inner_S_iters"] < a["inner_S_iters"]
+    assert b["inner_A_iters"] < a["inner_A_iters"]
