@@ -19,6 +19,8 @@
 // damped-Jacobi sweep from zero, residual restricted to the next level,
 // coarse correction prolonged and scaled, one damped-Jacobi sweep; the
 // coarsest level runs a fixed number of Jacobi sweeps inside one workgroup.
+// Scaling the coarse correction (by less than 2) keeps the cycle SPD and
+// offsets the weak coarse operators of piecewise-constant aggregation.
 // Nodes that are not unknowns (diagonal 0) are held at 0.
 #pragma once
 
@@ -129,135 +131,304 @@ struct MgOp {
     const void* Wz;
 };
 
-// Seven values of a plane's vector around node (i, j, k).
+// ---------------------------------------------------------------------------
+// Level 0 (the voxel grid), column sweeps.  The first Jacobi sweep from zero,
+// x0 = omega D^-1 b, is never stored: both kernels recompute it at the seven
+// points of a stencil from b and the diagonal.
+// ---------------------------------------------------------------------------
+
+// Level-0 operator of plane a at voxel X, given x at the seven points
+// (centre, -x, +x, -y, +y, -z, +z).  KIND A: (5 + s) x - sum of neighbours on
+// an active face (s = face state from the voxel's code), 0 otherwise.
+// KIND Shat: sum over the six faces of w (x_X - x_nbr), w = 1 / diag(A) of
+// the face (0 on an inactive face).
+template <class T, int KIND>
+__device__ __forceinline__ T mgf_apply(const T (&v)[7], int cX, int cxp, int cyp, int czp, int a) {
+    if (KIND == kMgFineA) {
+        const int sc = s_plane(cX, a);
+        const T nb = ((v[1] + v[2]) + (v[3] + v[4])) + (v[5] + v[6]);
+        return sc ? (T)(5 + sc) * v[0] - nb : T(0);
+    }
+    const T wxl = inv_diag_A_t<T>(sx_of(cX)), wyl = inv_diag_A_t<T>(sy_of(cX)), wzl = inv_diag_A_t<T>(sz_of(cX));
+    const T wxh = inv_diag_A_t<T>(sx_of(cxp)), wyh = inv_diag_A_t<T>(sy_of(cyp)), wzh = inv_diag_A_t<T>(sz_of(czp));
+    return ((wxl * (v[0] - v[1]) + wxh * (v[0] - v[2])) + (wyl * (v[0] - v[3]) + wyh * (v[0] - v[4]))) +
+           (wzl * (v[0] - v[5]) + wzh * (v[0] - v[6]));
+}
+
+// Diagonal data at the seven points of voxel n for the level-0 kernels: the
+// codes (KIND A: all seven, to form 1/D at each; KIND Shat: centre, +x, +y,
+// +z) and, for KIND Shat, 1/D from invd.
+template <class T, int KIND>
+struct MgfDiag {
+    int cd[7];
+    T inv[7];     // KIND Shat only
+};
+
+template <class T, int KIND>
+__device__ __forceinline__ void mgf_load_diag(MgfDiag<T, KIND>& m, const Nbr& n, const uint8_t* __restrict__ code,
+                                              const T* __restrict__ invd) {
+    const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
+    if (KIND == kMgFineA) {
+#pragma unroll
+        for (int t = 0; t < 7; ++t) m.cd[t] = code[idx[t]];
+    } else {
+        m.cd[0] = code[n.X];
+        m.cd[2] = code[n.xp];
+        m.cd[4] = code[n.yp];
+        m.cd[6] = code[n.zp];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) m.inv[t] = invd[idx[t]];
+    }
+}
+
+// values of one plane (pl = plane base) at the seven points
 template <class T>
-struct Seven {
-    T c, xm, xp, ym, yp, zm, zp;
+__device__ __forceinline__ void mgf_load7(T (&v)[7], const Nbr& n, const T* __restrict__ pl) {
+    const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
+#pragma unroll
+    for (int t = 0; t < 7; ++t) v[t] = pl[idx[t]];
+}
+
+// 1/D at point t of plane a
+template <class T, int KIND>
+__device__ __forceinline__ T mgf_inv(const MgfDiag<T, KIND>& m, int a, int t) {
+    if (KIND == kMgFineA) return inv_diag_A_t<T>(s_plane(m.cd[t], a));
+    return m.inv[t];
+}
+
+// b - A x0 at voxel n of plane a, x0 = omega D^-1 b
+template <class T, int KIND>
+__device__ __forceinline__ T mgf_residual0(const MgfDiag<T, KIND>& m, const T (&bv)[7], int a, T omega) {
+    T x0[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) x0[t] = omega * mgf_inv<T, KIND>(m, a, t) * bv[t];
+    return bv[0] - mgf_apply<T, KIND>(x0, m.cd[0], m.cd[2], m.cd[4], m.cd[6], a);
+}
+
+// bc = P^T (b - A x0), x0 = omega D^-1 b, from level 0 to level 1.  Sweep with
+// 32 x 8 columns (bxlog 5) and an even number of z-planes per block: a thread
+// sums the residual of its voxel over two consecutive planes, then the four
+// voxels of a 2 x 2 in-plane block (lanes i^1 and j^1 = lane^32 of one wave)
+// are added with shuffles and the lane of the even (i, j) stores the sum.
+template <class T, int KIND>
+__global__ void k_mgf_restrict(Sweep s, MgGrid cg, const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                               const T* __restrict__ b, T* __restrict__ bc, T omega, const CgState* st) {
+    if (st && st->done) return;
+    constexpr int NB = KIND == kMgFineA ? 3 : 1;
+    const Column c = sweep_column(s);
+    for (int k0 = c.k0; k0 < c.k1; k0 += 2) {
+        T acc[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) acc[a] = T(0);
+        if (c.valid) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const Nbr n = neighbours(s, c, k0 + u);
+                MgfDiag<T, KIND> m;
+                mgf_load_diag<T, KIND>(m, n, code, invd);
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    T bv[7];
+                    mgf_load7<T>(bv, n, b + (size_t)a * s.n3);
+                    acc[a] += mgf_residual0<T, KIND>(m, bv, a, omega);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            acc[a] += __shfl_xor(acc[a], 1, 64);
+            acc[a] += __shfl_xor(acc[a], 32, 64);
+        }
+        if (c.valid && !(c.i & 1) && !(c.j & 1)) {
+            const int C = (c.i >> 1) + cg.n * ((c.j >> 1) + cg.n * (k0 >> 1));
+#pragma unroll
+            for (int a = 0; a < NB; ++a) bc[(size_t)a * cg.n3 + C] = acc[a];
+        }
+    }
+}
+
+// Parents (level-1 nodes) of a voxel and of its neighbours across x, y and z:
+// of the two x-neighbours one shares the voxel's parent, the other lies in
+// the block across; likewise for y and z.
+struct MgParents {
+    int c;          // parent of the voxel
+    int x, y, z;    // parent of the block across x, y, z
+    bool xlo, ylo, zlo;  // voxel is the lower one of its pair (so -x lies across)
+};
+
+__device__ __forceinline__ MgParents mg_parents(int N, int cn, int i, int j, int k) {
+    MgParents q;
+    q.xlo = !(i & 1);
+    q.ylo = !(j & 1);
+    q.zlo = !(k & 1);
+    const int ci = i >> 1, cj = j >> 1, ck = k >> 1;
+    const int ai = q.xlo ? (i == 0 ? N - 1 : i - 1) >> 1 : (i == N - 1 ? 0 : i + 1) >> 1;
+    const int aj = q.ylo ? (j == 0 ? N - 1 : j - 1) >> 1 : (j == N - 1 ? 0 : j + 1) >> 1;
+    const int ak = q.zlo ? (k == 0 ? N - 1 : k - 1) >> 1 : (k == N - 1 ? 0 : k + 1) >> 1;
+    q.c = ci + cn * (cj + cn * ck);
+    q.x = ai + cn * (cj + cn * ck);
+    q.y = ci + cn * (aj + cn * ck);
+    q.z = ci + cn * (cj + cn * ak);
+    return q;
+}
+
+// scale * (P xc) at the seven points (centre, -x, +x, -y, +y, -z, +z)
+template <class T>
+__device__ __forceinline__ void mg_prolong7(const MgParents& q, const T (&xp)[4], T scale, T (&e)[7]) {
+    const T own = scale * xp[0], ax = scale * xp[1], ay = scale * xp[2], az = scale * xp[3];
+    e[0] = own;
+    e[1] = q.xlo ? ax : own;
+    e[2] = q.xlo ? own : ax;
+    e[3] = q.ylo ? ay : own;
+    e[4] = q.ylo ? own : ay;
+    e[5] = q.zlo ? az : own;
+    e[6] = q.zlo ? own : az;
+}
+
+// y = x' + omega D^-1 (b - A x'), x' = x0 + scale * P xc, x0 = omega D^-1 b,
+// on level 0 over the CG sweeps; nodes that are not unknowns (1/D = 0) are
+// held at 0 (a coarse correction also reaches them through their aggregate).
+// Writes the block's partial of (b, y) into part[slot][block].
+template <class T, int KIND>
+__global__ void k_mgf_postsmooth(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                                 const T* __restrict__ b, const T* __restrict__ xc, int cn, T scale, T omega,
+                                 T* __restrict__ y, double* part, int slot, const CgState* st) {
+    if (st && st->done) return;
+    constexpr int NB = KIND == kMgFineA ? 3 : 1;
+    const Column c = sweep_column(s);
+    const size_t cn3 = (size_t)cn * cn * cn;
+    double acc[1] = {0.0};
+    if (c.valid) {
+        for (int k = c.k0; k < c.k1; ++k) {
+            const Nbr n = neighbours(s, c, k);
+            const MgParents q = mg_parents(s.N, cn, c.i, c.j, k);
+            MgfDiag<T, KIND> m;
+            mgf_load_diag<T, KIND>(m, n, code, invd);
+            // KIND A: one plane at a time keeps the live values within the register budget
+#pragma unroll(KIND == kMgFineA ? 1 : NB)
+            for (int a = 0; a < NB; ++a) {
+                T bv[7];
+                mgf_load7<T>(bv, n, b + (size_t)a * s.n3);
+                const T* xa = xc + a * cn3;
+                const T xp[4] = {xa[q.c], xa[q.x], xa[q.y], xa[q.z]};
+                T e[7], v[7];
+                mg_prolong7<T>(q, xp, scale, e);
+#pragma unroll
+                for (int t = 0; t < 7; ++t) v[t] = omega * mgf_inv<T, KIND>(m, a, t) * bv[t] + e[t];
+                const T inv = mgf_inv<T, KIND>(m, a, 0);
+                const T ax = mgf_apply<T, KIND>(v, m.cd[0], m.cd[2], m.cd[4], m.cd[6], a);
+                const T yv = inv > T(0) ? v[0] + omega * inv * (bv[0] - ax) : T(0);
+                y[(size_t)a * s.n3 + n.X] = yv;
+                acc[0] += (double)bv[0] * (double)yv;
+            }
+        }
+    }
+    write_partials<1>(acc, part, slot, c.lb);
+}
+
+// ---------------------------------------------------------------------------
+// Levels >= 1 (assembled 7-point operators), one thread per node
+// ---------------------------------------------------------------------------
+
+// Coefficients, b and 1/D at the seven points of node (p; i, j, k)
+template <class T>
+struct MgcPoint {
+    T b[7], inv[7];
+    T d;            // diagonal at the node
+    T w[6];         // couplings to -x, +x, -y, +y, -z, +z
 };
 
 template <class T>
-__device__ __forceinline__ Seven<T> mg_load7(const MgGrid& g, const T* __restrict__ x, int p, int i, int j, int k) {
-    const T* xpl = x + (size_t)p * g.n3;
-    return {xpl[mg_idx(g, i, j, k)],     xpl[mg_idx(g, i - 1, j, k)], xpl[mg_idx(g, i + 1, j, k)],
-            xpl[mg_idx(g, i, j - 1, k)], xpl[mg_idx(g, i, j + 1, k)], xpl[mg_idx(g, i, j, k - 1)],
-            xpl[mg_idx(g, i, j, k + 1)]};
-}
-
-// (A v)_node and 1/D at node (p; i, j, k), given the seven values v.
-template <class T>
-__device__ __forceinline__ T mg_apply7(const MgGrid& g, const MgOp& op, const Seven<T>& v, int p, int i, int j, int k,
-                                       T* inv_diag) {
-    const int X = mg_idx(g, i, j, k);
-    if (op.code) {
-        const int cX = op.code[X];
-        if (op.kind == kMgFineShat) {
-            const T wxl = inv_diag_A_t<T>(sx_of(cX)), wyl = inv_diag_A_t<T>(sy_of(cX)),
-                    wzl = inv_diag_A_t<T>(sz_of(cX));
-            const T wxh = inv_diag_A_t<T>(sx_of(op.code[mg_idx(g, i + 1, j, k)])),
-                    wyh = inv_diag_A_t<T>(sy_of(op.code[mg_idx(g, i, j + 1, k)])),
-                    wzh = inv_diag_A_t<T>(sz_of(op.code[mg_idx(g, i, j, k + 1)]));
-            *inv_diag = ((const T*)op.invd)[X];
-            return ((wxl * (v.c - v.xm) + wxh * (v.c - v.xp)) + (wyl * (v.c - v.ym) + wyh * (v.c - v.yp))) +
-                   (wzl * (v.c - v.zm) + wzh * (v.c - v.zp));
-        }
-        const int s = s_plane(cX, p);
-        *inv_diag = inv_diag_A_t<T>(s);
-        const T nb = ((v.xm + v.xp) + (v.ym + v.yp)) + (v.zm + v.zp);
-        return s ? (T)(5 + s) * v.c - nb : T(0);
-    }
+__device__ __forceinline__ void mgc_load(MgcPoint<T>& m, const MgGrid& g, const MgOp& op, const T* __restrict__ b,
+                                         int p, int i, int j, int k) {
     const size_t o = (size_t)p * g.n3;
     const T* D = (const T*)op.D + o;
     const T* Wx = (const T*)op.Wx + o;
     const T* Wy = (const T*)op.Wy + o;
     const T* Wz = (const T*)op.Wz + o;
-    const T d = D[X];
-    *inv_diag = d > T(0) ? T(1) / d : T(0);
-    return d * v.c - (((Wx[X] * v.xm + Wx[mg_idx(g, i + 1, j, k)] * v.xp) +
-                       (Wy[X] * v.ym + Wy[mg_idx(g, i, j + 1, k)] * v.yp)) +
-                      (Wz[X] * v.zm + Wz[mg_idx(g, i, j, k + 1)] * v.zp));
-}
-
-template <class T>
-__device__ __forceinline__ T mg_inv_diag(const MgGrid& g, const MgOp& op, int p, int X) {
-    if (op.code) {
-        if (op.kind == kMgFineShat) return ((const T*)op.invd)[X];
-        return inv_diag_A_t<T>(s_plane(op.code[X], p));
+    const T* bp = b + o;
+    const int idx[7] = {mg_idx(g, i, j, k),     mg_idx(g, i - 1, j, k), mg_idx(g, i + 1, j, k), mg_idx(g, i, j - 1, k),
+                        mg_idx(g, i, j + 1, k), mg_idx(g, i, j, k - 1), mg_idx(g, i, j, k + 1)};
+    T dd[7];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        m.b[t] = bp[idx[t]];
+        dd[t] = D[idx[t]];
     }
-    const T d = ((const T*)op.D)[(size_t)p * g.n3 + X];
-    return d > T(0) ? T(1) / d : T(0);
+    m.w[0] = Wx[idx[0]];
+    m.w[1] = Wx[idx[2]];
+    m.w[2] = Wy[idx[0]];
+    m.w[3] = Wy[idx[4]];
+    m.w[4] = Wz[idx[0]];
+    m.w[5] = Wz[idx[6]];
+    m.d = dd[0];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) m.inv[t] = dd[t] > T(0) ? T(1) / dd[t] : T(0);
 }
 
-// x = omega D^-1 b (a first Jacobi sweep from zero)
 template <class T>
-__global__ void k_mg_presmooth(MgGrid g, MgOp op, const T* __restrict__ b, T* __restrict__ x, T omega,
+__device__ __forceinline__ T mgc_apply(const MgcPoint<T>& m, const T (&v)[7]) {
+    return m.d * v[0] - (((m.w[0] * v[1] + m.w[1] * v[2]) + (m.w[2] * v[3] + m.w[3] * v[4])) +
+                         (m.w[4] * v[5] + m.w[5] * v[6]));
+}
+
+// bc = P^T (b - A x0), x0 = omega D^-1 b, from level l to level l+1.  The
+// eight children of a coarse node sit in eight consecutive lanes (thread t:
+// coarse node t / 8, child t % 8) and are summed with shuffles.
+template <class T>
+__global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict__ b, T* __restrict__ bc, T omega,
                                const CgState* st) {
     if (st && st->done) return;
-    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < g.nb * g.n3; I += gridDim.x * blockDim.x) {
-        const int p = I / g.n3;
-        x[I] = omega * mg_inv_diag<T>(g, op, p, I - p * g.n3) * b[I];
-    }
-}
-
-// bc[I] = sum over the 8 children of (b - A x) (residual restricted to the next level)
-template <class T>
-__global__ void k_mg_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict__ b, const T* __restrict__ x,
-                              T* __restrict__ bc, const CgState* st) {
-    if (st && st->done) return;
-    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < cg.nb * cg.n3; I += gridDim.x * blockDim.x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int I = t >> 3, ch = t & 7;
+    T r = T(0);
+    if (I < cg.nb * cg.n3) {
         const int p = I / cg.n3, L = I - p * cg.n3;
-        const int ci = L % cg.n, cj = (L / cg.n) % cg.n, ck = L / cg.n2;
-        T acc = T(0);
-        for (int c = 0; c < 2; ++c)
-            for (int bb = 0; bb < 2; ++bb)
-                for (int a = 0; a < 2; ++a) {
-                    const int i = 2 * ci + a, j = 2 * cj + bb, k = 2 * ck + c;
-                    T inv;
-                    const Seven<T> v = mg_load7<T>(g, x, p, i, j, k);
-                    const T ax = mg_apply7<T>(g, op, v, p, i, j, k, &inv);
-                    acc += b[(size_t)p * g.n3 + mg_idx(g, i, j, k)] - ax;
-                }
-        bc[I] = acc;
+        const int i = 2 * (L % cg.n) + (ch & 1), j = 2 * ((L / cg.n) % cg.n) + ((ch >> 1) & 1),
+                  k = 2 * (L / cg.n2) + (ch >> 2);
+        MgcPoint<T> m;
+        mgc_load<T>(m, g, op, b, p, i, j, k);
+        T x0[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) x0[q] = omega * m.inv[q] * m.b[q];
+        r = m.b[0] - mgc_apply<T>(m, x0);
     }
+    r += __shfl_xor(r, 1, 64);
+    r += __shfl_xor(r, 2, 64);
+    r += __shfl_xor(r, 4, 64);
+    if (ch == 0 && I < cg.nb * cg.n3) bc[I] = r;
 }
 
-// y = x' + omega D^-1 (b - A x') with x' = x + scale * P xc (the coarse
-// correction added on the fly at the node and its neighbours).  With part !=
-// nullptr the block writes its partial of (b, y) into part[slot][blockIdx.x];
-// the grid then has exactly as many blocks as the CG sweeps, whose next kernel
-// re-adds these partials.
+// y = x' + omega D^-1 (b - A x'), x' = x0 + scale * P xc, x0 = omega D^-1 b,
+// on a level >= 1; nodes with D = 0 are held at 0.
 template <class T>
-__global__ void k_mg_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, const T* __restrict__ x,
-                                const T* __restrict__ xc, int cn, T scale, T omega, T* __restrict__ y, double* part,
-                                int slot, const CgState* st) {
+__global__ void k_mgc_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, const T* __restrict__ xc, int cn,
+                                 T scale, T omega, T* __restrict__ y, const CgState* st) {
     if (st && st->done) return;
-    double acc[1] = {0.0};
-    const int cn3 = cn * cn * cn;
-    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < g.nb * g.n3; I += gridDim.x * blockDim.x) {
-        const int p = I / g.n3, X = I - p * g.n3;
-        const int i = X % g.n, j = (X / g.n) % g.n, k = X / g.n2;
-        const T* xpl = x + (size_t)p * g.n3;
-        const T* cpl = xc + (size_t)p * cn3;
-        // corrected iterate at the seven points
-        auto corr = [=](int ii, int jj, int kk) -> T {
-            const int fi = wrapc(ii, g.n), fj = wrapc(jj, g.n), fk = wrapc(kk, g.n);
-            return xpl[fi + g.n * (fj + g.n * fk)] + scale * cpl[(fi >> 1) + cn * ((fj >> 1) + cn * (fk >> 1))];
-        };
-        const Seven<T> v = {corr(i, j, k),     corr(i - 1, j, k), corr(i + 1, j, k), corr(i, j - 1, k),
-                            corr(i, j + 1, k), corr(i, j, k - 1), corr(i, j, k + 1)};
-        T inv;
-        const T ax = mg_apply7<T>(g, op, v, p, i, j, k, &inv);
-        // a coarse correction also reaches nodes that share an aggregate with
-        // unknowns; nodes that are not unknowns (1/D = 0) are held at 0
-        const T yv = inv > T(0) ? v.c + omega * inv * (b[I] - ax) : T(0);
-        y[I] = yv;
-        acc[0] += (double)b[I] * (double)yv;
-    }
-    if (part) write_partials<1>(acc, part, slot, blockIdx.x);
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.nb * g.n3) return;
+    const int p = I / g.n3, X = I - p * g.n3;
+    const int i = X % g.n, j = (X / g.n) % g.n, k = X / g.n2;
+    MgcPoint<T> m;
+    mgc_load<T>(m, g, op, b, p, i, j, k);
+    const MgParents q = mg_parents(g.n, cn, i, j, k);
+    const T* xa = xc + (size_t)p * cn * cn * cn;
+    const T xp[4] = {xa[q.c], xa[q.x], xa[q.y], xa[q.z]};
+    T e[7], v[7];
+    mg_prolong7<T>(q, xp, scale, e);
+#pragma unroll
+    for (int t = 0; t < 7; ++t) v[t] = omega * m.inv[t] * m.b[t] + e[t];
+    const T ax = mgc_apply<T>(m, v);
+    y[I] = m.inv[0] > T(0) ? v[0] + omega * m.inv[0] * (m.b[0] - ax) : T(0);
 }
 
 // Coarsest level: `sweeps` damped-Jacobi sweeps from zero inside one workgroup
-// (x in LDS, double-buffered).  nb * n3 <= kMgCoarsestMax.
+// (x in LDS, double-buffered).  Each thread keeps the coefficients and
+// neighbour indices of its nodes in registers, so a sweep touches only LDS.
+// nb * n3 <= kMgCoarsestMax, at most kMgCoarsestPer nodes per thread.
 constexpr int kMgCoarsestMax = 2048;
+constexpr int kMgCoarsestThreads = 1024;
+constexpr int kMgCoarsestPer = kMgCoarsestMax / kMgCoarsestThreads;
 
 template <class T>
 __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __restrict__ xout, T omega, int sweeps,
@@ -265,25 +436,55 @@ __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __r
     if (st && st->done) return;
     __shared__ T xs[2][kMgCoarsestMax];
     const int n = g.nb * g.n3;
-    for (int I = threadIdx.x; I < n; I += blockDim.x) {
-        const int p = I / g.n3;
-        xs[0][I] = omega * mg_inv_diag<T>(g, op, p, I - p * g.n3) * b[I];
+    // per node: omega/D, b, the six couplings and the six neighbour slots
+    T wd[kMgCoarsestPer], bb[kMgCoarsestPer], w[kMgCoarsestPer][6], dg[kMgCoarsestPer];
+    int nbr[kMgCoarsestPer][6];
+#pragma unroll
+    for (int q = 0; q < kMgCoarsestPer; ++q) {
+        const int I = threadIdx.x + q * kMgCoarsestThreads;
+        const int Ic = I < n ? I : 0;
+        const int p = Ic / g.n3, X = Ic - p * g.n3;
+        const int i = X % g.n, j = (X / g.n) % g.n, k = X / g.n2;
+        const int base = p * g.n3;
+        nbr[q][0] = base + mg_idx(g, i - 1, j, k);
+        nbr[q][1] = base + mg_idx(g, i + 1, j, k);
+        nbr[q][2] = base + mg_idx(g, i, j - 1, k);
+        nbr[q][3] = base + mg_idx(g, i, j + 1, k);
+        nbr[q][4] = base + mg_idx(g, i, j, k - 1);
+        nbr[q][5] = base + mg_idx(g, i, j, k + 1);
+        // the coarsest level is always an assembled (coarse) level
+        const T* D = (const T*)op.D;
+        const T* Wx = (const T*)op.Wx;
+        const T* Wy = (const T*)op.Wy;
+        const T* Wz = (const T*)op.Wz;
+        dg[q] = D[Ic];
+        w[q][0] = Wx[Ic];
+        w[q][1] = Wx[nbr[q][1]];
+        w[q][2] = Wy[Ic];
+        w[q][3] = Wy[nbr[q][3]];
+        w[q][4] = Wz[Ic];
+        w[q][5] = Wz[nbr[q][5]];
+        wd[q] = dg[q] > T(0) ? omega / dg[q] : T(0);
+        bb[q] = b[Ic];
+        if (I < n) xs[0][I] = wd[q] * bb[q];
     }
     __syncthreads();
     int cur = 0;
     for (int it = 1; it < sweeps; ++it) {
-        for (int I = threadIdx.x; I < n; I += blockDim.x) {
-            const int p = I / g.n3, X = I - p * g.n3;
-            const int i = X % g.n, j = (X / g.n) % g.n, k = X / g.n2;
-            const Seven<T> v = mg_load7<T>(g, xs[cur], p, i, j, k);
-            T inv;
-            const T ax = mg_apply7<T>(g, op, v, p, i, j, k, &inv);
-            xs[cur ^ 1][I] = v.c + omega * inv * (b[I] - ax);
+#pragma unroll
+        for (int q = 0; q < kMgCoarsestPer; ++q) {
+            const int I = threadIdx.x + q * kMgCoarsestThreads;
+            if (I >= n) continue;
+            const T* x = xs[cur];
+            const T ax = dg[q] * x[I] - (((w[q][0] * x[nbr[q][0]] + w[q][1] * x[nbr[q][1]]) +
+                                          (w[q][2] * x[nbr[q][2]] + w[q][3] * x[nbr[q][3]])) +
+                                         (w[q][4] * x[nbr[q][4]] + w[q][5] * x[nbr[q][5]]));
+            xs[cur ^ 1][I] = x[I] + wd[q] * (bb[q] - ax);
         }
         __syncthreads();
         cur ^= 1;
     }
-    for (int I = threadIdx.x; I < n; I += blockDim.x) xout[I] = xs[cur][I];
+    for (int I = threadIdx.x; I < n; I += kMgCoarsestThreads) xout[I] = xs[cur][I];
 }
 
 // out = (float) in, flat

@@ -95,14 +95,15 @@ struct stokes_ctx {
         struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y; };
         std::vector<Lev64> l64;        // [1..levels]
         std::vector<Lev32> l32;
-        double *x0 = nullptr, *z = nullptr;   // fine level: presmoothed iterate, output
-        float *x0_32 = nullptr, *z32 = nullptr;
+        double* z = nullptr;           // fine level: output of the cycle
+        float* z32 = nullptr;
     };
     MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
     int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
-    double mg_omega = 0.8, mg_scale = 1.0;
+    double mg_omega = 0.8, mg_scale = 1.6;
     int mg_coarse_sweeps = 16;
+    Sweep msw{};                       // level-0 restriction sweep (even N)
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -158,6 +159,25 @@ Sweep make_sweep(int N, int target_blocks) {
     const int cols = s.gx * s.gy;
     int gz = std::max(1, std::min(N, (target_blocks + cols - 1) / cols));
     s.lz = (N + gz - 1) / gz;
+    s.gz = (N + s.lz - 1) / s.lz;
+    s.nblk = s.gx * s.gy * s.gz;
+    return s;
+}
+
+// Sweep of the level-0 restriction: 32 x 8 columns (a wave holds 2 x 2 voxel
+// blocks in lanes i^1 and i^32) and an even run of z-planes per block.
+// N must be even.
+Sweep make_mg_sweep(int N, int target_blocks) {
+    Sweep s{};
+    s.N = N;
+    s.N2 = N * N;
+    s.n3 = N * N * N;
+    s.bxlog = 5;
+    s.gx = (N + 31) / 32;
+    s.gy = (N + 7) / 8;
+    const int cols = s.gx * s.gy;
+    const int gz = std::max(1, std::min(N / 2, (target_blocks + cols - 1) / cols));
+    s.lz = 2 * ((N / 2 + gz - 1) / gz);
     s.gz = (N + s.lz - 1) / s.lz;
     s.nblk = s.gx * s.gy * s.gz;
     return s;
@@ -345,6 +365,8 @@ stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* 
 
 // ---- multigrid preconditioners ---------------------------------------------
 int flat_blocks(int n, int cap = 2048) { return std::max(1, std::min(cap, (n + kBlock - 1) / kBlock)); }
+// one thread per item (kernels without a grid-stride loop)
+unsigned exact_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 using MgHier = stokes_ctx::MgHier;
 
 // Levels: halve while the side is even and a level holds more than 512 nodes
@@ -371,7 +393,6 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
         const size_t m = (size_t)nb * h.grid[l].n3;
         for (double** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, m));
     }
-    ST_TRY(dev_alloc(c, &h.x0, (size_t)nb * c->n3));
     ST_TRY(dev_alloc(c, &h.z, (size_t)nb * c->n3));
     const int m1 = nb * h.grid[1].n3;
     hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
@@ -403,7 +424,6 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
         for (int q = 0; q < 4; ++q)
             hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m)), dim3(kBlock), 0, c->stream, m, src[q], dst[q]);
     }
-    ST_TRY(dev_alloc(c, &h.x0_32, (size_t)h.nb * c->n3));
     ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
@@ -421,8 +441,6 @@ MgView<float> mg_view(MgHier& h, int l, float) {
     auto& v = h.l32[l];
     return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y};
 }
-double* mg_fine_x(MgHier& h, double) { return h.x0; }
-float* mg_fine_x(MgHier& h, float) { return h.x0_32; }
 double* mg_out(MgHier& h, double) { return h.z; }
 float* mg_out(MgHier& h, float) { return h.z32; }
 
@@ -439,32 +457,42 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
         ops[l] = {nullptr, 0, nullptr, v.D, v.Wx, v.Wy, v.Wz};
     }
     auto nodes = [&](int l) { return h.nb * h.grid[l].n3; };
-    // descend: presmooth, restrict
-    for (int l = 0; l < L; ++l) {
-        const T* b = l == 0 ? b0 : mg_view(h, l, T()).b;
-        T* x = l == 0 ? mg_fine_x(h, T()) : mg_view(h, l, T()).x;
-        hipLaunchKernelGGL(k_mg_presmooth<T>, dim3(flat_blocks(nodes(l))), dim3(kBlock), 0, c->stream, h.grid[l],
-                           ops[l], b, x, omega, st);
-        hipLaunchKernelGGL(k_mg_restrict<T>, dim3(flat_blocks(nodes(l + 1))), dim3(kBlock), 0, c->stream, h.grid[l],
-                           h.grid[l + 1], ops[l], b, (const T*)x, mg_view(h, l + 1, T()).b, st);
+    const bool kindA = h.kind == kMgFineA;
+    // descend: residual of the first Jacobi sweep, restricted
+    {
+        const MgGrid& cg = h.grid[1];
+        T* bc = mg_view(h, 1, T()).b;
+        if (kindA)
+            hipLaunchKernelGGL((k_mgf_restrict<T, kMgFineA>), grid_of(c->msw), dim3(kBlock), 0, c->stream, c->msw, cg,
+                               c->code, invd0, b0, bc, omega, st);
+        else
+            hipLaunchKernelGGL((k_mgf_restrict<T, kMgFineShat>), grid_of(c->msw), dim3(kBlock), 0, c->stream, c->msw,
+                               cg, c->code, invd0, b0, bc, omega, st);
     }
+    for (int l = 1; l < L; ++l)
+        hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0, c->stream,
+                           h.grid[l], h.grid[l + 1], ops[l], (const T*)mg_view(h, l, T()).b, mg_view(h, l + 1, T()).b,
+                           omega, st);
     // coarsest: Jacobi sweeps in one workgroup, result in x
     {
         auto v = mg_view(h, L, T());
-        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1), dim3(1024), 0, c->stream, h.grid[L], ops[L], (const T*)v.b,
-                           v.x, omega, c->mg_coarse_sweeps, st);
+        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1), dim3(kMgCoarsestThreads), 0, c->stream, h.grid[L], ops[L],
+                           (const T*)v.b, v.x, omega, c->mg_coarse_sweeps, st);
     }
     // ascend: prolong the correction and postsmooth; the result of level l is
     // in its y (level 0: z0)
-    for (int l = L - 1; l >= 0; --l) {
-        const T* b = l == 0 ? b0 : mg_view(h, l, T()).b;
-        const T* x = l == 0 ? mg_fine_x(h, T()) : mg_view(h, l, T()).x;
-        const T* xc = (l + 1 == L) ? mg_view(h, L, T()).x : mg_view(h, l + 1, T()).y;
-        T* y = l == 0 ? z0 : mg_view(h, l, T()).y;
-        const int grid = l == 0 ? c->sw.nblk : flat_blocks(nodes(l));
-        hipLaunchKernelGGL(k_mg_postsmooth<T>, dim3(grid), dim3(kBlock), 0, c->stream, h.grid[l], ops[l], b, x, xc,
-                           h.grid[l + 1].n, scale, omega, y, l == 0 ? c->part : nullptr, kRZ, st);
+    auto coarse_x = [&](int l) -> const T* { return l == L ? mg_view(h, L, T()).x : mg_view(h, l, T()).y; };
+    for (int l = L - 1; l >= 1; --l) {
+        auto v = mg_view(h, l, T());
+        hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream, h.grid[l],
+                           ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y, st);
     }
+    if (kindA)
+        hipLaunchKernelGGL((k_mgf_postsmooth<T, kMgFineA>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+                           c->code, invd0, b0, coarse_x(1), h.grid[1].n, scale, omega, z0, c->part, kRZ, st);
+    else
+        hipLaunchKernelGGL((k_mgf_postsmooth<T, kMgFineShat>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+                           c->code, invd0, b0, coarse_x(1), h.grid[1].n, scale, omega, z0, c->part, kRZ, st);
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -703,6 +731,7 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     const int64_t n3 = c->n3;
     c->sw = make_sweep(N, c->sweep_blocks);
     if (c->sw.nblk > kMaxBlocks) return STOKES_E_LIMIT;
+    if (N % 2 == 0) c->msw = make_mg_sweep(N, c->sweep_blocks);
     c->wpr = (N + 31) / 32;
 
     // remaining-fluid bitmask

@@ -90,7 +90,8 @@ def test_mixed_oblique_slits(P):
         rep = s.solve(P.STOKES_SIMPLE, 1e-8)
     ws = channel_widths(N, [3, 4, 6])
     assert rep["mean_u"][0] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-8)
-    assert abs(rep["mean_u"][1]) < 1e-9
+    # u_y vanishes in the exact solution; the solve leaves it at the outer tolerance's level
+    assert abs(rep["mean_u"][1]) < 10 * 1e-8 * rep["mean_u"][0]
 
 
 def test_mixed_matches_fp64_gpu(P):
