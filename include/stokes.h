@@ -210,13 +210,17 @@ stokes_status stokes_apply_device(stokes_ctx *ctx, int op, const double *in, dou
 
 /* info[0..11]: N, fluid voxels (as given), fluid voxels kept, surface voxels,
  * components (as given), components kept, active x/y/z faces (3 values),
- * device bytes held, 0, 0. */
+ * device bytes held, coarse levels of the multigrid hierarchy for the SIMPLE
+ * matrix and for A (0: none -- odd N, or the coarsest level would not fit one
+ * workgroup -- and that inner solve uses Jacobi-PCG). */
 stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
 
 /* Device time of the inner-loop kernels since the last call for that kernel,
  * measured with HIP events around the sampled launches (see "kernel_timing")
  * on the context's stream.  kernel: 0 = A direction, 1 = A stencil,
- * 2 = A update, 3 = SIMPLE direction, 4 = SIMPLE stencil, 5 = SIMPLE update.  Returns the total
+ * 2 = A update, 3 = SIMPLE direction, 4 = SIMPLE stencil, 5 = SIMPLE update,
+ * and the voxel-level multigrid kernels: 6 = A restriction, 7 = A smoothing,
+ * 8 = SIMPLE restriction, 9 = SIMPLE smoothing.  Returns the total
  * milliseconds and the number of timed launches (launches queued after
  * convergence return at once and are counted too), and the algorithmic bytes one launch
  * moves (each input read once, each output written once, in FP64). */

@@ -155,98 +155,6 @@ __device__ __forceinline__ T mgf_apply(const T (&v)[7], int cX, int cxp, int cyp
            (wzl * (v[0] - v[5]) + wzh * (v[0] - v[6]));
 }
 
-// Diagonal data at the seven points of voxel n for the level-0 kernels: the
-// codes (KIND A: all seven, to form 1/D at each; KIND Shat: centre, +x, +y,
-// +z) and, for KIND Shat, 1/D from invd.
-template <class T, int KIND>
-struct MgfDiag {
-    int cd[7];
-    T inv[7];     // KIND Shat only
-};
-
-template <class T, int KIND>
-__device__ __forceinline__ void mgf_load_diag(MgfDiag<T, KIND>& m, const Nbr& n, const uint8_t* __restrict__ code,
-                                              const T* __restrict__ invd) {
-    const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
-    if (KIND == kMgFineA) {
-#pragma unroll
-        for (int t = 0; t < 7; ++t) m.cd[t] = code[idx[t]];
-    } else {
-        m.cd[0] = code[n.X];
-        m.cd[2] = code[n.xp];
-        m.cd[4] = code[n.yp];
-        m.cd[6] = code[n.zp];
-#pragma unroll
-        for (int t = 0; t < 7; ++t) m.inv[t] = invd[idx[t]];
-    }
-}
-
-// values of one plane (pl = plane base) at the seven points
-template <class T>
-__device__ __forceinline__ void mgf_load7(T (&v)[7], const Nbr& n, const T* __restrict__ pl) {
-    const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
-#pragma unroll
-    for (int t = 0; t < 7; ++t) v[t] = pl[idx[t]];
-}
-
-// 1/D at point t of plane a
-template <class T, int KIND>
-__device__ __forceinline__ T mgf_inv(const MgfDiag<T, KIND>& m, int a, int t) {
-    if (KIND == kMgFineA) return inv_diag_A_t<T>(s_plane(m.cd[t], a));
-    return m.inv[t];
-}
-
-// b - A x0 at voxel n of plane a, x0 = omega D^-1 b
-template <class T, int KIND>
-__device__ __forceinline__ T mgf_residual0(const MgfDiag<T, KIND>& m, const T (&bv)[7], int a, T omega) {
-    T x0[7];
-#pragma unroll
-    for (int t = 0; t < 7; ++t) x0[t] = omega * mgf_inv<T, KIND>(m, a, t) * bv[t];
-    return bv[0] - mgf_apply<T, KIND>(x0, m.cd[0], m.cd[2], m.cd[4], m.cd[6], a);
-}
-
-// bc = P^T (b - A x0), x0 = omega D^-1 b, from level 0 to level 1.  Sweep with
-// 32 x 8 columns (bxlog 5) and an even number of z-planes per block: a thread
-// sums the residual of its voxel over two consecutive planes, then the four
-// voxels of a 2 x 2 in-plane block (lanes i^1 and j^1 = lane^32 of one wave)
-// are added with shuffles and the lane of the even (i, j) stores the sum.
-template <class T, int KIND>
-__global__ void k_mgf_restrict(Sweep s, MgGrid cg, const uint8_t* __restrict__ code, const T* __restrict__ invd,
-                               const T* __restrict__ b, T* __restrict__ bc, T omega, const CgState* st) {
-    if (st && st->done) return;
-    constexpr int NB = KIND == kMgFineA ? 3 : 1;
-    const Column c = sweep_column(s);
-    for (int k0 = c.k0; k0 < c.k1; k0 += 2) {
-        T acc[NB];
-#pragma unroll
-        for (int a = 0; a < NB; ++a) acc[a] = T(0);
-        if (c.valid) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const Nbr n = neighbours(s, c, k0 + u);
-                MgfDiag<T, KIND> m;
-                mgf_load_diag<T, KIND>(m, n, code, invd);
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    T bv[7];
-                    mgf_load7<T>(bv, n, b + (size_t)a * s.n3);
-                    acc[a] += mgf_residual0<T, KIND>(m, bv, a, omega);
-                }
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a) {
-            acc[a] += __shfl_xor(acc[a], 1, 64);
-            acc[a] += __shfl_xor(acc[a], 32, 64);
-        }
-        if (c.valid && !(c.i & 1) && !(c.j & 1)) {
-            const int C = (c.i >> 1) + cg.n * ((c.j >> 1) + cg.n * (k0 >> 1));
-#pragma unroll
-            for (int a = 0; a < NB; ++a) bc[(size_t)a * cg.n3 + C] = acc[a];
-        }
-    }
-}
-
 // Parents (level-1 nodes) of a voxel and of its neighbours across x, y and z:
 // of the two x-neighbours one shares the voxel's parent, the other lies in
 // the block across; likewise for y and z.
@@ -285,45 +193,157 @@ __device__ __forceinline__ void mg_prolong7(const MgParents& q, const T (&xp)[4]
     e[6] = q.zlo ? own : az;
 }
 
-// y = x' + omega D^-1 (b - A x'), x' = x0 + scale * P xc, x0 = omega D^-1 b,
-// on level 0 over the CG sweeps; nodes that are not unknowns (1/D = 0) are
-// held at 0 (a coarse correction also reaches them through their aggregate).
-// Writes the block's partial of (b, y) into part[slot][block].
+// ---------------------------------------------------------------------------
+// Level 0, LDS-tiled: each block marches its BX x BY column through z.  The
+// smoothed iterate (x0 = omega D^-1 b for the restriction, x' = x0 + scale P xc
+// for the post-smoothing) is computed once per point: a thread keeps its own
+// column's values at k-1, k, k+1 in registers, and plane k of the tile plus
+// a one-voxel ring (computed by the first 2 (BX + BY) threads) goes through
+// LDS (double-buffered, one barrier per plane) for the in-plane neighbours.
+// Lanes past the box edge compute the value at their wrapped position, which
+// is exactly the periodic neighbour of the last voxel inside.
+// ---------------------------------------------------------------------------
+constexpr int kMgTile = 396;   // (BX + 2) (BY + 2) for BX x BY = 64 x 4 (32 x 8 needs 340)
+
+// Per-point data of the level-0 smoothed iterate.
 template <class T, int KIND>
-__global__ void k_mgf_postsmooth(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ invd,
-                                 const T* __restrict__ b, const T* __restrict__ xc, int cn, T scale, T omega,
-                                 T* __restrict__ y, double* part, int slot, const CgState* st) {
-    if (st && st->done) return;
-    constexpr int NB = KIND == kMgFineA ? 3 : 1;
-    const Column c = sweep_column(s);
-    const size_t cn3 = (size_t)cn * cn * cn;
-    double acc[1] = {0.0};
-    if (c.valid) {
-        for (int k = c.k0; k < c.k1; ++k) {
-            const Nbr n = neighbours(s, c, k);
-            const MgParents q = mg_parents(s.N, cn, c.i, c.j, k);
-            MgfDiag<T, KIND> m;
-            mgf_load_diag<T, KIND>(m, n, code, invd);
-            // KIND A: one plane at a time keeps the live values within the register budget
-#pragma unroll(KIND == kMgFineA ? 1 : NB)
-            for (int a = 0; a < NB; ++a) {
-                T bv[7];
-                mgf_load7<T>(bv, n, b + (size_t)a * s.n3);
-                const T* xa = xc + a * cn3;
-                const T xp[4] = {xa[q.c], xa[q.x], xa[q.y], xa[q.z]};
-                T e[7], v[7];
-                mg_prolong7<T>(q, xp, scale, e);
+struct MgfPt {
+    static constexpr int NB = KIND == kMgFineA ? 3 : 1;
+    int cd;          // code of the voxel
+    T b[NB];         // b of each plane
+    T inv[NB];       // 1 / D of each plane
+    T x[NB];         // smoothed iterate
+};
+
+template <class T, int KIND, bool POST>
+__device__ __forceinline__ void mgf_point(MgfPt<T, KIND>& q, int N, int cn, int i, int j, int k,
+                                          const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                                          const T* __restrict__ b, const T* __restrict__ xc, T scale, T omega) {
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    const int X = i + N * (j + N * k);
+    const size_t n3 = (size_t)N * N * N;
+    q.cd = code[X];
+    T e[NB];
+    if (POST) {
+        const size_t cn3 = (size_t)cn * cn * cn;
+        const int C = (i >> 1) + cn * ((j >> 1) + cn * (k >> 1));
 #pragma unroll
-                for (int t = 0; t < 7; ++t) v[t] = omega * mgf_inv<T, KIND>(m, a, t) * bv[t] + e[t];
-                const T inv = mgf_inv<T, KIND>(m, a, 0);
-                const T ax = mgf_apply<T, KIND>(v, m.cd[0], m.cd[2], m.cd[4], m.cd[6], a);
-                const T yv = inv > T(0) ? v[0] + omega * inv * (bv[0] - ax) : T(0);
-                y[(size_t)a * s.n3 + n.X] = yv;
-                acc[0] += (double)bv[0] * (double)yv;
+        for (int a = 0; a < NB; ++a) e[a] = xc[a * cn3 + C];
+    }
+    if (KIND == kMgFineShat) q.inv[0] = invd[X];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) q.b[a] = b[a * n3 + X];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        if (KIND == kMgFineA) q.inv[a] = inv_diag_A_t<T>(s_plane(q.cd, a));
+        q.x[a] = omega * q.inv[a] * q.b[a];
+        if (POST) q.x[a] += scale * e[a];
+    }
+}
+
+// POST = false: bc = P^T (b - A x0) into level 1 (Sweep: bxlog 5, even z-runs;
+// the 2 x 2 x 2 sum uses two consecutive planes and lanes i^1, i^32).
+// POST = true: y = x' + omega D^-1 (b - A x'), nodes with 1/D = 0 held at 0,
+// and the block's partial of (b, y) into part[slot][block] (Sweep: the CG's).
+template <class T, int KIND, bool POST>
+__global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uint8_t* __restrict__ code,
+                                                      const T* __restrict__ invd, const T* __restrict__ b,
+                                                      const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
+                                                      double* part, int slot, const CgState* st) {
+    if (st && st->done) return;
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    __shared__ T tile[2][NB][kMgTile];
+    const int N = s.N;
+    const int lb = xcd_remap((int)blockIdx.x, s.nblk);
+    const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
+    const int bx = lb % s.gx, t = lb / s.gx, by = t % s.gy, bz = t / s.gy;
+    const int tx = (int)threadIdx.x & (BX - 1), ty = (int)threadIdx.x >> s.bxlog;
+    const int gi = bx * BX + tx, gj = by * BY + ty;
+    const bool valid = gi < N && gj < N;
+    const int wi = gi % N, wj = gj % N;
+    const int k0 = bz * s.lz, k1 = min(N, k0 + s.lz);
+    // ring point of this thread (if any): left, right, bottom, top edges
+    const int H = 2 * (BX + BY);
+    const int h = (int)threadIdx.x;
+    int hx = 0, hy = 0;
+    if (h < BY) { hx = -1; hy = h; }
+    else if (h < 2 * BY) { hx = BX; hy = h - BY; }
+    else if (h < 2 * BY + BX) { hx = h - 2 * BY; hy = -1; }
+    else { hx = h - 2 * BY - BX; hy = BY; }
+    const int hi = ((bx * BX + hx) % N + N) % N, hj = ((by * BY + hy) % N + N) % N;
+    const int hslot = (hy + 1) * W + (hx + 1);
+    const int own = (ty + 1) * W + (tx + 1);
+    auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
+
+    MgfPt<T, KIND> cur, nxt;
+    T xprev[NB];
+    {
+        MgfPt<T, KIND> pv;
+        mgf_point<T, KIND, POST>(pv, N, cn, wi, wj, zw(k0 - 1), code, invd, b, xc, scale, omega);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
+    }
+    mgf_point<T, KIND, POST>(cur, N, cn, wi, wj, k0, code, invd, b, xc, scale, omega);
+    double acc = 0.0;       // POST: partial of (b, y)
+    T rsum[NB];             // restriction: residual summed over the plane pair
+#pragma unroll
+    for (int a = 0; a < NB; ++a) rsum[a] = T(0);
+    int buf = 0;
+    for (int k = k0; k < k1; ++k) {
+        mgf_point<T, KIND, POST>(nxt, N, cn, wi, wj, zw(k + 1), code, invd, b, xc, scale, omega);
+        if (h < H) {
+            MgfPt<T, KIND> hp;
+            mgf_point<T, KIND, POST>(hp, N, cn, hi, hj, k, code, invd, b, xc, scale, omega);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) tile[buf][a][hslot] = hp.x[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) tile[buf][a][own] = cur.x[a];
+        // KIND Shat: the +x and +y faces' codes
+        int cxp = 0, cyp = 0;
+        if (KIND == kMgFineShat) {
+            const int X = wi + N * (wj + N * k);
+            cxp = code[X - wi + (wi == N - 1 ? 0 : wi + 1)];
+            cyp = code[X + (wj == N - 1 ? -(N - 1) * N : N)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const T* tl = tile[buf][a];
+            const T v[7] = {cur.x[a], tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev[a], nxt.x[a]};
+            const T ax = mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a);
+            if (POST) {
+                const T yv = cur.inv[a] > T(0) ? v[0] + omega * cur.inv[a] * (cur.b[a] - ax) : T(0);
+                if (valid) {
+                    out[(size_t)a * s.n3 + wi + N * (wj + N * k)] = yv;
+                    acc += (double)cur.b[a] * (double)yv;
+                }
+            } else {
+                rsum[a] += cur.b[a] - ax;
             }
         }
+        if (!POST && (k & 1)) {
+            // pair complete: 2 x 2 in-plane sum and store
+            const int cN = N >> 1;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                T r = rsum[a];
+                r += __shfl_xor(r, 1, 64);
+                r += __shfl_xor(r, 32, 64);
+                if (valid && !(gi & 1) && !(gj & 1))
+                    out[(size_t)a * cN * cN * cN + (gi >> 1) + cN * ((gj >> 1) + cN * (k >> 1))] = r;
+                rsum[a] = T(0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = cur.x[a];
+        cur = nxt;
+        buf ^= 1;
     }
-    write_partials<1>(acc, part, slot, c.lb);
+    if (POST) {
+        double v1[1] = {acc};
+        write_partials<1>(v1, part, slot, lb);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -44,14 +44,21 @@ constexpr int kCompBlocks = 256;
 
 // kinds of timed kernels and their algorithmic bytes per voxel (FP64)
 enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeSStencil = 4, kTimeSUpdate = 5,
-       kTimeKinds = 6 };
+       kTimeMgARestrict = 6, kTimeMgASmooth = 7, kTimeMgSRestrict = 8, kTimeMgSSmooth = 9, kTimeKinds = 10 };
 // A dir     : r, d read (3 planes each), code byte read; d written
 // A stencil : d read, code byte read; q written
 // A update  : x, d, r, q read, code byte read; x, r written
 // S dir     : r, inverse diagonal, d read; d written
 // S stencil : d read, code byte read; q written
 // S update  : inverse diagonal, x, d, r, q read; x, r written
-constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1, 6 * 8 + 1, 18 * 8 + 1, 4 * 8, 2 * 8 + 1, 7 * 8};
+// multigrid, level 0 (1/8 of a value per voxel for the level-1 vector):
+// A restriction   : b (3 planes), code byte read; level-1 b written
+// A smoothing     : b (3 planes), code byte, level-1 x read; y (3 planes) written
+// S restriction   : b, inverse diagonal, code byte read; level-1 b written
+// S smoothing     : b, inverse diagonal, code byte, level-1 x read; y written
+constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,    6 * 8 + 1,         18 * 8 + 1,   4 * 8,    2 * 8 + 1,
+                                              7 * 8,        3 * 8 + 1 + 3,     6 * 8 + 1 + 3, 2 * 8 + 1 + 1,
+                                              3 * 8 + 1 + 1};
 
 }  // namespace
 
@@ -125,7 +132,7 @@ struct stokes_ctx {
     int max_outer = 5000, max_inner = 100000;
     int stop_prec = 0, check_every = 0, true_velocity = 0;
     int timing = 0;                // 0: off; n: time every n-th launch of each inner-loop kernel
-    int64_t timing_seen[6] = {0, 0, 0, 0, 0, 0};
+    int64_t timing_seen[kTimeKinds] = {};
 
     // adaptive polling
     int last_it[2] = {0, 0};
@@ -139,8 +146,8 @@ struct stokes_ctx {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
     size_t ev_used = 0;
-    double timing_ms[6] = {0, 0, 0, 0, 0, 0};
-    int64_t timing_launches[6] = {0, 0, 0, 0, 0, 0};
+    double timing_ms[kTimeKinds] = {};
+    int64_t timing_launches[kTimeKinds] = {};
 };
 
 namespace {
@@ -462,12 +469,15 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     {
         const MgGrid& cg = h.grid[1];
         T* bc = mg_view(h, 1, T()).b;
+        bool open;
+        ST_TRY(time_begin(c, kindA ? kTimeMgARestrict : kTimeMgSRestrict, &open));
         if (kindA)
-            hipLaunchKernelGGL((k_mgf_restrict<T, kMgFineA>), grid_of(c->msw), dim3(kBlock), 0, c->stream, c->msw, cg,
-                               c->code, invd0, b0, bc, omega, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, false>), grid_of(c->msw), dim3(kBlock), 0, c->stream,
+                               c->msw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         else
-            hipLaunchKernelGGL((k_mgf_restrict<T, kMgFineShat>), grid_of(c->msw), dim3(kBlock), 0, c->stream, c->msw,
-                               cg, c->code, invd0, b0, bc, omega, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, false>), grid_of(c->msw), dim3(kBlock), 0, c->stream,
+                               c->msw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
+        ST_TRY(time_end(c, open));
     }
     for (int l = 1; l < L; ++l)
         hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0, c->stream,
@@ -487,12 +497,15 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
         hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream, h.grid[l],
                            ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y, st);
     }
+    bool open;
+    ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : kTimeMgSSmooth, &open));
     if (kindA)
-        hipLaunchKernelGGL((k_mgf_postsmooth<T, kMgFineA>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
-                           c->code, invd0, b0, coarse_x(1), h.grid[1].n, scale, omega, z0, c->part, kRZ, st);
+        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+                           h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
     else
-        hipLaunchKernelGGL((k_mgf_postsmooth<T, kMgFineShat>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
-                           c->code, invd0, b0, coarse_x(1), h.grid[1].n, scale, omega, z0, c->part, kRZ, st);
+        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+                           h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
+    ST_TRY(time_end(c, open));
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -1383,8 +1396,8 @@ stokes_status stokes_info(stokes_ctx* c, int64_t info[12]) {
     info[7] = c->nface[1];
     info[8] = c->nface[2];
     info[9] = c->device_bytes;
-    info[10] = 0;
-    info[11] = 0;
+    info[10] = c->mgS.levels;
+    info[11] = c->mgA.levels;
     return STOKES_OK;
 }
 

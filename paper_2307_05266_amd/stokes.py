@@ -217,11 +217,13 @@ def stokes_info(ctx):
     info = (ctypes.c_int64 * 12)()
     _check(load().stokes_info(ctx, info), "stokes_info")
     keys = ["N", "nfluid_in", "nfluid", "nsurf", "ncomp_all", "ncomp_kept", "nface_x", "nface_y", "nface_z",
-            "device_bytes"]
+            "device_bytes", "mg_levels_S", "mg_levels_A"]
     return {k: int(info[i]) for i, k in enumerate(keys)}
 
 
-KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil", "k_cgS_update"]
+KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil", "k_cgS_update",
+                "k_mgf_tiled<A,restrict>", "k_mgf_tiled<A,smooth>", "k_mgf_tiled<S,restrict>",
+                "k_mgf_tiled<S,smooth>"]
 
 
 def stokes_kernel_timing(ctx, kernel):

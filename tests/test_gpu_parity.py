@@ -337,11 +337,13 @@ def test_full_size_solution_satisfies_equations(P, pc):
         assert abs(p[comp == c].mean()) < 1e-10 * max(np.abs(p).max(), 1.0)
 
 
-@pytest.mark.parametrize("N,seed", [(24, 3), (48, 5)])
+# 10: one coarse level, columns wider than the box; 36: the last column of
+# 32-wide tiles runs past the box edge (wrapped lanes feed the periodic ring)
+@pytest.mark.parametrize("N,seed", [(10, 1), (24, 3), (36, 2), (48, 5)])
 def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
     """The SIMPLE inner solve with the multigrid preconditioner (default) and with
     Jacobi reach the same outer trajectory: same outer count (+-1), same k."""
-    m = spheres(N, 3.0, 0.45, seed)
+    m = spheres(N, 3.0 if N > 10 else 1.5, 0.45, seed)
     with P.Stokes(m) as s:
         s.set_option("mg", 0)
         s.set_option("mg_A", 0)
@@ -349,9 +351,41 @@ def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
         s.set_option("mg", 1)
         s.set_option("mg_A", 1)
         b = s.solve(P.STOKES_SIMPLE, 1e-8)
+        info = s.info()
     say(f"    jacobi: outer={a['outer_iters']} innerA={a['inner_A_iters']} innerS={a['inner_S_iters']}  "
-        f"mg: outer={b['outer_iters']} innerA={b['inner_A_iters']} innerS={b['inner_S_iters']}")
+        f"mg: outer={b['outer_iters']} innerA={b['inner_A_iters']} innerS={b['inner_S_iters']}  "
+        f"levels S={info['mg_levels_S']} A={info['mg_levels_A']}")
     assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
     assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
+    # halving stops at an odd side; the coarsest level must fit one workgroup
+    # (n^3 <= 2048 for the SIMPLE matrix, 3 n^3 <= 2048 for A's three planes)
+    n = N
+    while n % 2 == 0 and n // 2 >= 2 and n ** 3 > 512:
+        n //= 2
+    assert info["mg_levels_S"] == (0 if n == N or n ** 3 > 2048 else (N // n).bit_length() - 1)
+    assert info["mg_levels_A"] == (0 if n == N or 3 * n ** 3 > 2048 else (N // n).bit_length() - 1)
+    assert info["mg_levels_S"] > 0
     assert b["inner_S_iters"] < a["inner_S_iters"]
-    assert b["inner_A_iters"] < a["inner_A_iters"]
+    if info["mg_levels_A"] > 0:
+        assert b["inner_A_iters"] < a["inner_A_iters"]
+    else:
+        assert b["inner_A_iters"] == a["inner_A_iters"]
+
+
+def test_kernel_timing_counts_every_kind(P):
+    """Sampled HIP-event timing covers the six CG kernels and the four voxel-level
+    multigrid kernels; bytes per launch follow the per-voxel byte model."""
+    from paper_2307_05266_amd.stokes import KERNEL_NAMES
+    N = 32
+    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26]
+    with P.Stokes(spheres(N, 3.0, 0.5, 1)) as s:
+        s.set_option("kernel_timing", 1)
+        s.solve(P.STOKES_SIMPLE, 1e-8)
+        for kind, name in enumerate(KERNEL_NAMES):
+            ms, n, nbytes = s.kernel_timing(kind)
+            say(f"    {name}: {n} launches {ms:.3f} ms")
+            assert n > 0 and ms > 0.0, name
+            assert nbytes == per_voxel[kind] * N ** 3
+            assert s.kernel_timing(kind)[1] == 0   # reset by the read
+        with pytest.raises(P.StokesError):
+            s.kernel_timing(len(KERNEL_NAMES))
