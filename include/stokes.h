@@ -124,6 +124,26 @@ stokes_status stokes_setup_ex(stokes_ctx **ctx, const uint8_t *mask, int N, cons
                               unsigned flags);
 
 /*
+ * stokes_setup_on_stream -- as stokes_setup_ex, with all of the context's
+ * device work, including setup, on `stream` (a hipStream_t, not NULL), and its
+ * device memory allocated and freed in that stream's order (stream-ordered
+ * allocation), so that contexts on different streams never wait on each
+ * other's allocations.  The stream must outlive the context.  Used by the
+ * request server; any caller that owns a stream may use it.
+ */
+stokes_status stokes_setup_on_stream(stokes_ctx **ctx, const uint8_t *mask, int N, const double force[3],
+                                     unsigned flags, void *stream);
+
+/*
+ * stokes_estimate_bytes -- upper bound of the device bytes a context for an
+ * N^3 box holds (info[9] after setup, plus the FP32 vectors when precision =
+ * 1 is used), with the component arrays at their 2048-component limit.
+ * Host-only arithmetic; needs no GPU.  STOKES_E_ARG for a bad N, flags or
+ * precision (0 or 1) or a NULL bytes.
+ */
+stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_t *bytes);
+
+/*
  * stokes_preprocess -- the host-only part of stokes_setup (Sec. 2.1-2.2,
  * eqs. porosity, s-t-v-ration, surface_area); needs no GPU.
  *   mask, N, force, flags  as for stokes_setup_ex.
@@ -150,8 +170,13 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "stop_prec"   0: stop on ||r||/||r0|| (default); 1: on ||z||/||z0||
  *                 (the preconditioned norm of Algorithm 1)
  *   "check_every" inner iterations queued between convergence checks (default 0 = adaptive)
- *   "kernel_timing" n > 0: time every n-th launch of each inner-loop kernel with
- *                 HIP events (0 = off, the default)
+ *   "kernel_timing" n > 0: every n-th iteration of each inner solve is launched
+ *                 eagerly with each of its kernels bracketed by HIP events
+ *                 (0 = off, the default); see stokes_kernel_timing
+ *   "graphs"      1 (default): each inner solve's iteration (CG kernels and
+ *                 V-cycle) is captured once as a HIP graph and replayed; 0:
+ *                 launched kernel by kernel.  Results are bitwise the same.
+ *                 Any stokes_set_option call drops the captured graphs.
  *   "true_velocity" 1: after the solve, recompute u = A^{-1}(f - B^T p)
  *   "sweep_blocks" number of workgroups a sweep aims for (default 1024)
  *   "mg", "mg_A"  1 (default): precondition the inner CG with the SIMPLE matrix

@@ -9,8 +9,11 @@ its sources (csrc/), the build script and a thin ctypes binding.
 """
 
 from .stokes import (  # noqa: F401
+    Server,
     Stokes,
     StokesError,
+    stokes_estimate_bytes,
+    stokes_setup_on_stream,
     load,
     stokes_apply,
     stokes_apply_device,

@@ -67,7 +67,8 @@ struct CgState {
     double zrel;      // ||z_j|| / ||z_0||
     double dq;        // (d_j, A d_j)
     double eps;
-    int it;           // operator applications so far
+    int it;           // operator applications so far = index j of the next iteration
+    int jcur;         // j of the iteration in progress (set by its direction kernel)
     int done;         // 1: stop (converged, capped or broken down)
     int status;       // 0 ok, 1 iteration cap, -4 breakdown
     int maxit;
@@ -396,8 +397,15 @@ __global__ void k_mask_cells(Sweep s, const uint32_t* __restrict__ bits, int wpr
 // keeps the stencil at one input array (measured faster on gfx950).
 // ---------------------------------------------------------------------------
 // Returns true when this iteration should not run; block 0 records why.
-// first: j == 0, then d_0 = z_0 and z0 = ||z_0|| is recorded.
-__device__ __forceinline__ bool cg_dir_scalars(CgState* st, const double* part, int nblk, int j, double* beta_out) {
+// The iteration index j lives in the state, so a launch sequence is the same
+// for every iteration (and can be replayed as a graph): the direction kernel
+// takes j = it and publishes it as jcur for the update kernel, whose block 0
+// advances it (no kernel both reads and writes the field another block reads).
+// j == 0: d_0 = z_0, and z0 = ||z_0|| is recorded.
+__device__ __forceinline__ bool cg_dir_scalars(CgState* st, const double* part, int nblk, double* beta_out,
+                                               int* j_out) {
+    const int j = st->it;
+    *j_out = j;
     const int slots[2] = {kRZ, kZZ};
     double tot[2];
     read_totals<2>(part, slots, nblk, tot);
@@ -432,13 +440,14 @@ __device__ __forceinline__ bool cg_dir_scalars(CgState* st, const double* part, 
         st->rho[j & 1] = rho;
         st->beta = beta;
         st->zrel = zrel;
+        st->jcur = j;
     }
     *beta_out = beta;
     return false;
 }
 
-__device__ __forceinline__ bool cg_update_scalars(CgState* st, const double* part, int nblk, int j,
-                                                  double* alpha_out) {
+__device__ __forceinline__ bool cg_update_scalars(CgState* st, const double* part, int nblk, double* alpha_out) {
+    const int j = st->jcur;
     const int slots[1] = {kDQ};
     double tot[1];
     read_totals<1>(part, slots, nblk, tot);
@@ -516,10 +525,11 @@ __device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(cod
 // multigrid-preconditioned residual, three planes)
 template <class T>
 __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ r, T* __restrict__ d,
-                          CgState* st, double* part, int j, const T* __restrict__ zpre) {
+                          CgState* st, double* part, const T* __restrict__ zpre) {
     if (st->done) return;
     double beta_d;
-    if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
+    int j;
+    if (cg_dir_scalars(st, part, s.nblk, &beta_d, &j)) return;
     const T beta = (T)beta_d;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -603,10 +613,10 @@ __global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const T
 
 template <class T>
 __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __restrict__ x, T* __restrict__ r,
-                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part, int j) {
+                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
     if (st->done) return;
     double alpha_d;
-    if (cg_update_scalars(st, part, s.nblk, j, &alpha_d)) return;
+    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
     const T alpha = (T)alpha_d;
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
@@ -684,10 +694,11 @@ __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b,
 // multigrid-preconditioned residual)
 template <class T>
 __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restrict__ r, T* __restrict__ d,
-                          CgState* st, double* part, int j, const T* __restrict__ zpre) {
+                          CgState* st, double* part, const T* __restrict__ zpre) {
     if (st->done) return;
     double beta_d;
-    if (cg_dir_scalars(st, part, s.nblk, j, &beta_d)) return;
+    int j;
+    if (cg_dir_scalars(st, part, s.nblk, &beta_d, &j)) return;
     const T beta = (T)beta_d;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -760,10 +771,10 @@ __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const T
 
 template <class T>
 __global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict__ x, T* __restrict__ r,
-                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part, int j) {
+                             const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
     if (st->done) return;
     double alpha_d;
-    if (cg_update_scalars(st, part, s.nblk, j, &alpha_d)) return;
+    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
     const T alpha = (T)alpha_d;
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};

@@ -10,10 +10,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,6 +42,7 @@ using namespace stokes;
 namespace {
 
 constexpr int kMaxN = 800;
+using GraphKey = std::array<uintptr_t, 8>;
 constexpr int kCompBlocks = 256;
 
 // kinds of timed kernels and their algorithmic bytes per voxel (FP64)
@@ -116,6 +119,7 @@ struct stokes_ctx {
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
     std::vector<void*> allocations;
     int64_t device_bytes = 0;
+    bool async_alloc = false;      // allocations ordered on `stream` (stokes_setup_on_stream)
     CgState* host_state = nullptr; // pinned
     double* host_part = nullptr;   // pinned [3 * kMaxBlocks]
     int sweep_blocks = 1024;
@@ -131,8 +135,13 @@ struct stokes_ctx {
     double eps_A = 1e-12, eps_S = 1e-12;
     int max_outer = 5000, max_inner = 100000;
     int stop_prec = 0, check_every = 0, true_velocity = 0;
-    int timing = 0;                // 0: off; n: time every n-th launch of each inner-loop kernel
-    int64_t timing_seen[kTimeKinds] = {};
+    int timing = 0;                // 0: off; n: time every n-th iteration of each inner solve
+    int64_t timing_seen[2] = {};   // iterations seen per inner solve (0: A, 1: SIMPLE)
+    bool time_iter = false;        // the iteration being launched is a timed one
+    // captured inner iterations (HIP graphs), keyed by solver variant and vectors
+    int use_graphs = 1;
+    hipStream_t cap_stream = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
 
     // adaptive polling
     int last_it[2] = {0, 0};
@@ -194,7 +203,10 @@ template <class T>
 stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
     void* m = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    if (hipMalloc(&m, bytes) != hipSuccess) return STOKES_E_NOMEM;
+    // contexts set up on a stream allocate and free in that stream's order, so
+    // concurrent contexts never wait on each other's allocations
+    const hipError_t e = c->async_alloc ? hipMallocAsync(&m, bytes, c->stream) : hipMalloc(&m, bytes);
+    if (e != hipSuccess) return STOKES_E_NOMEM;
     c->allocations.push_back(m);
     c->device_bytes += (int64_t)bytes;
     *ptr = static_cast<T*>(m);
@@ -202,7 +214,12 @@ stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
 }
 
 void release(stokes_ctx* c) {
-    for (void* m : c->allocations) (void)hipFree(m);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+    for (void* m : c->allocations) (void)(c->async_alloc ? hipFreeAsync(m, c->stream) : hipFree(m));
+    if (c->async_alloc && c->stream) (void)hipStreamSynchronize(c->stream);
     c->allocations.clear();
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
@@ -215,11 +232,13 @@ void release(stokes_ctx* c) {
 dim3 grid_of(const Sweep& s) { return dim3((unsigned)s.nblk); }
 
 // ---- inner solves -----------------------------------------------------------
-// Only every `timing`-th launch of a kind is bracketed, so the events barely
-// perturb the run they measure; the open flag tells time_end whether to close.
+// With kernel timing on, every `timing`-th iteration of an inner solve runs
+// eagerly with each of its kernels bracketed by HIP events (the others are
+// untimed, or replayed as a graph), so the events barely perturb the run they
+// measure; the open flag tells time_end whether to close.
 stokes_status time_begin(stokes_ctx* c, int kind, bool* open) {
     *open = false;
-    if (!c->timing || (c->timing_seen[kind]++ % c->timing) != 0) return STOKES_OK;
+    if (!c->timing || !c->time_iter) return STOKES_OK;
     *open = true;
     if (c->ev_used + 2 > c->ev.size()) {
         for (int q = 0; q < 512; ++q) {
@@ -284,9 +303,85 @@ InnerA<float> bufA32(stokes_ctx* c) { return {c->fx32, c->fr32, c->fd32, c->fq32
 InnerS<double> bufS64(stokes_ctx* c) { return {c->zs, c->sr, c->sd, c->sq, c->invdS}; }
 InnerS<float> bufS32(stokes_ctx* c) { return {c->zs32, c->sr32, c->sd32, c->sq32, c->invdS32}; }
 
+// ---- iteration driver ---------------------------------------------------------
+// An inner solve launches the same sequence every iteration (the iteration
+// index lives in the device state), so the sequence is captured once per
+// context and vector set as a HIP graph and replayed; the host polls the device
+// state between batches.  Captures run on a private stream (the context's
+// stream may be the legacy null stream, which cannot capture); the graph is
+// launched on the context's stream.
+void drop_graphs(stokes_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+template <class Body>
+stokes_status capture_graph(stokes_ctx* c, Body& body, hipGraphExec_t* out) {
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t keep = c->stream;
+    c->stream = c->cap_stream;
+    const stokes_status st = body();
+    c->stream = keep;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st != STOKES_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != STOKES_OK ? st : STOKES_E_DEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return ei == hipSuccess ? STOKES_OK : STOKES_E_DEVICE;
+}
+
+// Run inner-CG iterations of solve `which` (0: A, 1: SIMPLE) until the device
+// state says done.  key identifies the launch sequence (solver variant and the
+// vectors it touches) for the graph cache.
+template <class Body>
+stokes_status run_inner(stokes_ctx* c, int which, const GraphKey& key, Body body, int* iters, int* status) {
+    hipGraphExec_t g = nullptr;
+    if (c->use_graphs) {
+        auto it = c->graphs.find(key);
+        if (it != c->graphs.end()) {
+            g = it->second;
+        } else {
+            ST_TRY(capture_graph(c, body, &g));
+            c->graphs[key] = g;
+        }
+    }
+    int batch = first_batch(c, which);
+    CgState h{};
+    for (;;) {
+        for (int t = 0; t < batch; ++t) {
+            c->time_iter = c->timing && (c->timing_seen[which]++ % c->timing) == 0;
+            if (g && !c->time_iter) {
+                HIP_TRY(hipGraphLaunch(g, c->stream));
+            } else {
+                ST_TRY(body());
+            }
+            c->time_iter = false;
+        }
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(c, which, &h));
+        if (h.done) break;
+        batch = next_batch(c);
+    }
+    c->last_it[which] = h.it;
+    *iters = h.it;
+    *status = h.status;
+    return STOKES_OK;
+}
+
+template <class T>
+GraphKey graph_key(int variant, const void* a, const void* b, const void* cc, const void* d, const void* e,
+                   const void* f) {
+    return {(uintptr_t)variant, (uintptr_t)sizeof(T), (uintptr_t)a, (uintptr_t)b, (uintptr_t)cc, (uintptr_t)d,
+            (uintptr_t)e, (uintptr_t)f};
+}
+
 // Solve A x = b on the faces (b: an FP64 face vector, or nullptr for the
-// uniform force).  Iteration j launches the dir, stencil and update kernels;
-// the host polls the device state between batches.
+// uniform force), Jacobi-preconditioned.  One iteration: direction, stencil
+// and update kernels.
 template <class T>
 stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
@@ -294,41 +389,31 @@ stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int*
     hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
                        c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
-    int batch = first_batch(c, 0);
-    int j = 0;
-    CgState h{};
-    for (;;) {
-        for (int t = 0; t < batch; ++t, ++j) {
-            bool open;
-            ST_TRY(time_begin(c, kTimeADir, &open));
-            hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st,
-                               c->part, j, (const T*)nullptr);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeAStencil, &open));
-            hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                               c->part);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeAUpdate, &open));
-            hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d,
-                               v.q, st, c->part, j);
-            ST_TRY(time_end(c, open));
-        }
-        HIP_TRY(hipGetLastError());
-        ST_TRY(read_state(c, 0, &h));
-        if (h.done) break;
-        batch = next_batch(c);
-    }
-    c->last_it[0] = h.it;
-    *iters = h.it;
-    *status = h.status;
-    return STOKES_OK;
+    auto body = [c, s, st, v]() -> stokes_status {
+        bool open;
+        ST_TRY(time_begin(c, kTimeADir, &open));
+        hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st, c->part,
+                           (const T*)nullptr);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeAStencil, &open));
+        hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+                           c->part);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeAUpdate, &open));
+        hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d, v.q,
+                           st, c->part);
+        ST_TRY(time_end(c, open));
+        return STOKES_OK;
+    };
+    return run_inner(c, 0, graph_key<T>(0, v.x, v.r, v.d, v.q, nullptr, nullptr), body, iters, status);
 }
 
 stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
     return cg_A<double>(c, bufA64(c), b, eps, iters, status);
 }
 
-// Solve Shat x = b on the cells (b: an FP64 cell vector, already projected).
+// Solve Shat x = b on the cells (b: an FP64 cell vector, already projected),
+// Jacobi-preconditioned.
 template <class T>
 stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
@@ -336,34 +421,23 @@ stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int*
     hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
-    int batch = first_batch(c, 1);
-    int j = 0;
-    CgState h{};
-    for (;;) {
-        for (int t = 0; t < batch; ++t, ++j) {
-            bool open;
-            ST_TRY(time_begin(c, kTimeSDir, &open));
-            hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st,
-                               c->part, j, (const T*)nullptr);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeSStencil, &open));
-            hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                               c->part);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeSUpdate, &open));
-            hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d,
-                               v.q, st, c->part, j);
-            ST_TRY(time_end(c, open));
-        }
-        HIP_TRY(hipGetLastError());
-        ST_TRY(read_state(c, 1, &h));
-        if (h.done) break;
-        batch = next_batch(c);
-    }
-    c->last_it[1] = h.it;
-    *iters = h.it;
-    *status = h.status;
-    return STOKES_OK;
+    auto body = [c, s, st, v]() -> stokes_status {
+        bool open;
+        ST_TRY(time_begin(c, kTimeSDir, &open));
+        hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st, c->part,
+                           (const T*)nullptr);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeSStencil, &open));
+        hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+                           c->part);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeSUpdate, &open));
+        hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d, v.q,
+                           st, c->part);
+        ST_TRY(time_end(c, open));
+        return STOKES_OK;
+    };
+    return run_inner(c, 1, graph_key<T>(1, v.x, v.r, v.d, v.q, v.invd, nullptr), body, iters, status);
 }
 
 stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
@@ -378,22 +452,27 @@ using MgHier = stokes_ctx::MgHier;
 
 // Levels: halve while the side is even and a level holds more than 512 nodes
 // per plane; the coarsest level must fit one workgroup's LDS.
+// Sides of the levels of a hierarchy with nb planes on an N^3 box (level 0
+// first); a single entry when there is no hierarchy.
+std::vector<int> mg_plan(int N, int nb) {
+    std::vector<int> ns{N};
+    int n = N;
+    while (n % 2 == 0 && n / 2 >= 2 && n * n * n > 512) {
+        n /= 2;
+        ns.push_back(n);
+    }
+    if (ns.size() < 2 || (int64_t)nb * n * n * n > kMgCoarsestMax) ns.resize(1);
+    return ns;
+}
+
 stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     h.levels = 0;
     h.nb = nb;
     h.kind = kind;
     h.grid.clear();
-    int n = c->N;
-    h.grid.push_back({n, n * n, n * n * n, nb});
-    while (n % 2 == 0 && n / 2 >= 2 && n * n * n > 512) {
-        n /= 2;
-        h.grid.push_back({n, n * n, n * n * n, nb});
-    }
+    for (int n : mg_plan(c->N, nb)) h.grid.push_back({n, n * n, n * n * n, nb});
     const int L = (int)h.grid.size() - 1;
-    if (L < 1 || nb * h.grid[L].n3 > kMgCoarsestMax) {
-        h.grid.resize(1);
-        return STOKES_OK;
-    }
+    if (L < 1) return STOKES_OK;
     h.l64.assign(L + 1, {});
     for (int l = 1; l <= L; ++l) {
         auto& lv = h.l64[l];
@@ -511,7 +590,8 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
 }
 
 // Multigrid-preconditioned CG with the SIMPLE matrix; the stopping test stays
-// on the Jacobi-scaled residual ||D^-1 r|| / ||D^-1 r_0||.
+// on the Jacobi-scaled residual ||D^-1 r|| / ||D^-1 r_0||.  One iteration:
+// direction, stencil, update, then the V-cycle that forms the next z.
 template <class T>
 stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
     const Sweep& s = c->sw;
@@ -521,35 +601,23 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     ST_TRY(vcycle<T>(c, c->mgS, v.r, v.invd, z, nullptr));
-    int batch = first_batch(c, 1);
-    int j = 0;
-    CgState h{};
-    for (;;) {
-        for (int t = 0; t < batch; ++t, ++j) {
-            bool open;
-            ST_TRY(time_begin(c, kTimeSDir, &open));
-            hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st,
-                               c->part, j, (const T*)z);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeSStencil, &open));
-            hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                               c->part);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeSUpdate, &open));
-            hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d,
-                               v.q, st, c->part, j);
-            ST_TRY(time_end(c, open));
-            ST_TRY(vcycle<T>(c, c->mgS, v.r, v.invd, z, st));
-        }
-        HIP_TRY(hipGetLastError());
-        ST_TRY(read_state(c, 1, &h));
-        if (h.done) break;
-        batch = next_batch(c);
-    }
-    c->last_it[1] = h.it;
-    *iters = h.it;
-    *status = h.status;
-    return STOKES_OK;
+    auto body = [c, s, st, v, z]() -> stokes_status {
+        bool open;
+        ST_TRY(time_begin(c, kTimeSDir, &open));
+        hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st, c->part,
+                           (const T*)z);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeSStencil, &open));
+        hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+                           c->part);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeSUpdate, &open));
+        hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d, v.q,
+                           st, c->part);
+        ST_TRY(time_end(c, open));
+        return vcycle<T>(c, c->mgS, v.r, v.invd, z, st);
+    };
+    return run_inner(c, 1, graph_key<T>(2, v.x, v.r, v.d, v.q, v.invd, z), body, iters, status);
 }
 
 // Multigrid-preconditioned CG with A (three planes); stopping test on the
@@ -563,35 +631,23 @@ stokes_status cg_A_mg(stokes_ctx* c, InnerA<T> v, const double* b, double eps, i
                        c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     ST_TRY(vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, nullptr));
-    int batch = first_batch(c, 0);
-    int j = 0;
-    CgState h{};
-    for (;;) {
-        for (int t = 0; t < batch; ++t, ++j) {
-            bool open;
-            ST_TRY(time_begin(c, kTimeADir, &open));
-            hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st,
-                               c->part, j, (const T*)z);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeAStencil, &open));
-            hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                               c->part);
-            ST_TRY(time_end(c, open));
-            ST_TRY(time_begin(c, kTimeAUpdate, &open));
-            hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d,
-                               v.q, st, c->part, j);
-            ST_TRY(time_end(c, open));
-            ST_TRY(vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, st));
-        }
-        HIP_TRY(hipGetLastError());
-        ST_TRY(read_state(c, 0, &h));
-        if (h.done) break;
-        batch = next_batch(c);
-    }
-    c->last_it[0] = h.it;
-    *iters = h.it;
-    *status = h.status;
-    return STOKES_OK;
+    auto body = [c, s, st, v, z]() -> stokes_status {
+        bool open;
+        ST_TRY(time_begin(c, kTimeADir, &open));
+        hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st, c->part,
+                           (const T*)z);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeAStencil, &open));
+        hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+                           c->part);
+        ST_TRY(time_end(c, open));
+        ST_TRY(time_begin(c, kTimeAUpdate, &open));
+        hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d, v.q,
+                           st, c->part);
+        ST_TRY(time_end(c, open));
+        return vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, st);
+    };
+    return run_inner(c, 0, graph_key<T>(3, v.x, v.r, v.d, v.q, nullptr, z), body, iters, status);
 }
 
 // precision-generic dispatch between the multigrid and Jacobi inner solves
@@ -846,7 +902,8 @@ stokes_status stokes_preprocess(const uint8_t* mask, int N, const double force[3
     return STOKES_OK;
 }
 
-stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, const double force[3], unsigned flags) {
+static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
+                                  unsigned flags, hipStream_t stream) {
     if (!out) return STOKES_E_ARG;
     ST_TRY(check_inputs(mask, N, force, flags));
     const int64_t n3 = (int64_t)N * N * N;
@@ -857,6 +914,8 @@ stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, cons
     c->n3 = n3;
     for (int a = 0; a < 3; ++a) c->force[a] = force[a];
     c->setup_flags = flags;
+    c->stream = stream;
+    c->async_alloc = stream != nullptr;
     stokes_status st;
     try {
         st = setup_impl(c, mask);
@@ -872,8 +931,45 @@ stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, cons
     return STOKES_OK;
 }
 
+stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, const double force[3], unsigned flags) {
+    return setup_common(out, mask, N, force, flags, nullptr);
+}
+
 stokes_status stokes_setup(stokes_ctx** out, const uint8_t* mask, int N, const double force[3]) {
-    return stokes_setup_ex(out, mask, N, force, 0u);
+    return setup_common(out, mask, N, force, 0u, nullptr);
+}
+
+stokes_status stokes_setup_on_stream(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
+                                     unsigned flags, void* stream) {
+    if (!stream) return STOKES_E_ARG;
+    return setup_common(out, mask, N, force, flags, (hipStream_t)stream);
+}
+
+// Mirrors the allocations of setup_impl, build_mg, ensure_mixed_buffers and
+// build_mg32, with the component arrays at their limit and the label array
+// present, so the result bounds what a context holds.
+stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_t* bytes) {
+    if (!bytes || N < 2 || N > kMaxN || (flags & ~STOKES_KEEP_ALL_COMPONENTS) || (precision != 0 && precision != 1))
+        return STOKES_E_ARG;
+    const int64_t n3 = (int64_t)N * N * N, wpr = (N + 31) / 32;
+    auto blk = [](int64_t count, int64_t size) { return std::max<int64_t>(count, 1) * size; };
+    const int64_t K = kMaxCompLds;
+    int64_t t = blk((int64_t)N * N * wpr, 4) + blk(n3, 1) + blk(K, 8) + blk((int64_t)kCompBlocks * K, 8) +
+                blk(K, 8) + blk(n3, 2);
+    t += 5 * blk(3 * n3, 8) + 9 * blk(n3, 8);
+    t += blk(2, sizeof(CgState)) + blk((int64_t)kNumSlots * kMaxBlocks, 8) + blk(3 * (int64_t)kMaxBlocks, 8);
+    for (int nb : {1, 3}) {
+        const std::vector<int> ns = mg_plan(N, nb);
+        if (ns.size() < 2) continue;
+        for (int prec = 0; prec <= precision; ++prec) {
+            const int64_t w = prec == 0 ? 8 : 4;
+            for (size_t l = 1; l < ns.size(); ++l) t += 7 * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
+            t += blk(nb * n3, w);   // cycle output on level 0
+        }
+    }
+    if (precision == 1) t += 4 * blk(3 * n3, 4) + 5 * blk(n3, 4);
+    *bytes = t;
+    return STOKES_OK;
 }
 
 stokes_status stokes_set_stream(stokes_ctx* c, void* stream) {
@@ -903,6 +999,8 @@ static stokes_status ensure_mixed_buffers(stokes_ctx* c) {
 stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     if (!c || !key || !std::isfinite(v)) return STOKES_E_ARG;
     const std::string k(key);
+    // captured iterations bake in launch shapes and multigrid parameters
+    drop_graphs(c);
     if (k == "eps_A") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_A = v; }
     else if (k == "eps_S") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_S = v; }
     else if (k == "max_outer") { if (v < 1 || v > 1e7) return STOKES_E_ARG; c->max_outer = (int)v; }
@@ -934,7 +1032,9 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         if (sw.nblk > kMaxBlocks) return STOKES_E_ARG;
         c->sweep_blocks = (int)v;
         c->sw = sw;
+        if (c->N % 2 == 0) c->msw = make_mg_sweep(c->N, (int)v);
     }
+    else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }
     else return STOKES_E_ARG;
     return STOKES_OK;
 }

@@ -1,4 +1,4 @@
-"""Thin ctypes binding of libstokes.so (include/stokes.h).
+"""Thin ctypes binding of libstokes.so (include/stokes.h, include/stokes_server.h).
 
 Argument marshalling only: every step of the solve runs in the HIP library.
 The functions keep the C names; `Stokes` wraps one context.  torch is
@@ -31,7 +31,12 @@ EXPORTED = [
     "stokes_setup", "stokes_setup_ex", "stokes_set_stream", "stokes_set_option", "stokes_solve",
     "stokes_permeability", "stokes_get_report", "stokes_history", "stokes_get_fields",
     "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
-    "stokes_destroy", "stokes_status_str", "stokes_preprocess",
+    "stokes_destroy", "stokes_status_str", "stokes_preprocess", "stokes_setup_on_stream",
+    "stokes_estimate_bytes",
+]
+EXPORTED_SERVER = [
+    "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
+    "stokes_server_clock", "stokes_server_destroy",
 ]
 
 
@@ -54,6 +59,18 @@ class StokesReport(ctypes.Structure):
             v = getattr(self, name)
             d[name] = list(v) if name == "mean_u" else v
         return d
+
+
+class StokesRequestResult(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64), ("status", ctypes.c_int), ("N", ctypes.c_int), ("k_hat", ctypes.c_double),
+        ("outer_iters", ctypes.c_int), ("inner_A_iters", ctypes.c_int), ("inner_S_iters", ctypes.c_int),
+        ("rel_res", ctypes.c_double), ("div_norm", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+        ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class StokesError(RuntimeError):
@@ -93,6 +110,14 @@ def load():
         "stokes_destroy": ([vp], None),
         "stokes_status_str": ([ip], ctypes.c_char_p),
         "stokes_preprocess": ([vp, ip, dp, ctypes.c_uint, i64p, vp, vp], ip),
+        "stokes_setup_on_stream": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint, vp], ip),
+        "stokes_estimate_bytes": ([ip, ctypes.c_uint, ip, i64p], ip),
+        "stokes_server_create": ([ctypes.POINTER(vp), ip, ctypes.c_int64], ip),
+        "stokes_server_submit": ([vp, vp, ip, dp, ip, ctypes.c_double, ip, i64p], ip),
+        "stokes_server_wait": ([vp, ctypes.c_int64, ctypes.POINTER(StokesRequestResult)], ip),
+        "stokes_server_stats": ([vp, i64p], ip),
+        "stokes_server_clock": ([vp], ctypes.c_double),
+        "stokes_server_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -290,6 +315,77 @@ class Stokes:
         if getattr(self, "_ctx", None):
             stokes_destroy(self._ctx)
             self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stokes_estimate_bytes(N, precision=0, flags=0):
+    """Upper bound of the device bytes of a context for an N^3 box (host-only)."""
+    out = ctypes.c_int64()
+    _check(load().stokes_estimate_bytes(int(N), ctypes.c_uint(flags), int(precision), ctypes.byref(out)),
+           "stokes_estimate_bytes")
+    return out.value
+
+
+def stokes_setup_on_stream(mask, N, force, flags, stream):
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    f = (ctypes.c_double * 3)(*[float(x) for x in force])
+    ctx = ctypes.c_void_p()
+    _check(load().stokes_setup_on_stream(ctypes.byref(ctx), mask.ctypes.data, int(N), f, ctypes.c_uint(flags),
+                                         ctypes.c_void_p(stream)), "stokes_setup_on_stream")
+    return ctx
+
+
+SERVER_STATS = ["submitted", "completed", "queued", "running", "bytes_in_use", "peak_bytes", "peak_running",
+                "budget"]
+
+
+class Server:
+    """Request server (include/stokes_server.h): `slots` workers, each with its
+    own stream, admit queued solves as slots and HBM budget free up."""
+
+    def __init__(self, slots, hbm_budget_bytes):
+        lib = load()
+        self._srv = ctypes.c_void_p()
+        _check(lib.stokes_server_create(ctypes.byref(self._srv), int(slots), ctypes.c_int64(int(hbm_budget_bytes))),
+               "stokes_server_create")
+
+    def submit(self, mask, force=(1.0, 0.0, 0.0), precond=STOKES_SIMPLE, tol=1e-8, precision=1):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        N = int(mask.shape[0])
+        f = (ctypes.c_double * 3)(*[float(x) for x in force])
+        rid = ctypes.c_int64()
+        _check(load().stokes_server_submit(self._srv, mask.ctypes.data, N, f, int(precond), float(tol),
+                                           int(precision), ctypes.byref(rid)), "stokes_server_submit")
+        return rid.value
+
+    def wait(self, rid):
+        out = StokesRequestResult()
+        _check(load().stokes_server_wait(self._srv, ctypes.c_int64(rid), ctypes.byref(out)), "stokes_server_wait")
+        return out.to_dict()
+
+    def stats(self):
+        st = (ctypes.c_int64 * 8)()
+        _check(load().stokes_server_stats(self._srv, st), "stokes_server_stats")
+        return {k: int(st[i]) for i, k in enumerate(SERVER_STATS)}
+
+    def clock(self):
+        return load().stokes_server_clock(self._srv)
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            load().stokes_server_destroy(self._srv)
+            self._srv = None
 
     def __enter__(self):
         return self

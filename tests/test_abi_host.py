@@ -13,7 +13,7 @@ import oracle
 from synth import grf, slits, spheres
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "stokes.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("stokes.h", "stokes_server.h")]
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +24,7 @@ def P():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(stokes_[a-z_]+)\s*\(", src)))
 
@@ -37,11 +37,13 @@ def test_header_declares_expected_entry_points():
 
 def test_library_exports_every_declared_symbol(P):
     from paper_2307_05266_amd.stokes import LIB_PATH, EXPORTED
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["stokes.h", "stokes_server.h"]
     out = subprocess.run(["nm", "-D", "--defined-only", LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r"\bT (stokes_[a-z_]+)\b", out))
     for name in declared_functions():
         assert name in exported, name
-    assert set(EXPORTED) == set(declared_functions())
+    from paper_2307_05266_amd.stokes import EXPORTED_SERVER
+    assert set(EXPORTED) | set(EXPORTED_SERVER) == set(declared_functions())
 
 
 def test_status_strings(P):
@@ -103,3 +105,21 @@ def test_preprocess_slit_normal_force_removes_everything(P):
     from paper_2307_05266_amd.stokes import stokes_preprocess
     g = stokes_preprocess(slits(16, 4, axis=2), 16, (0.0, 0.0, 1.0))
     assert g["nfluid"] == 0 and g["ncomp_kept"] == 0 and g["ncomp_all"] > 0
+
+
+def test_estimate_bytes_host_only(P):
+    """The admission bound is host arithmetic: it grows with N, the mixed path's
+    FP32 vectors add to it, and bad arguments are rejected."""
+    from paper_2307_05266_amd.stokes import StokesError
+    est = [P.stokes_estimate_bytes(N) for N in (8, 16, 32, 64, 128)]
+    assert all(a < b for a, b in zip(est, est[1:]))
+    for N in (16, 32, 128, 256):
+        e64, e32 = P.stokes_estimate_bytes(N, 0), P.stokes_estimate_bytes(N, 1)
+        assert e32 > e64
+        # dominant terms: 5 face and 9 cell FP64 vectors, 4 face and 5 cell FP32 vectors
+        n3 = N ** 3
+        assert e64 >= (5 * 3 + 9) * 8 * n3
+        assert e32 - e64 >= (4 * 3 + 5) * 4 * n3
+    for bad in [(1, 0, 0), (801, 0, 0), (32, 2, 0), (32, 0, 2)]:
+        with pytest.raises(StokesError):
+            P.stokes_estimate_bytes(bad[0], precision=bad[2], flags=bad[1])

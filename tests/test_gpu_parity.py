@@ -389,3 +389,28 @@ def test_kernel_timing_counts_every_kind(P):
             assert s.kernel_timing(kind)[1] == 0   # reset by the read
         with pytest.raises(P.StokesError):
             s.kernel_timing(len(KERNEL_NAMES))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager_launches(P, precision):
+    """Inner iterations replayed from captured HIP graphs give bitwise the same
+    solve as kernel-by-kernel launches, on every replay (three solves in a row,
+    with eager work and host synchronisation between them), and with timed eager
+    iterations mixed into the replays."""
+    m = spheres(32, 3.0, 0.5, 11)
+    with P.Stokes(m, precision=precision) as s:
+        s.set_option("graphs", 0)
+        ref = s.solve(P.STOKES_SIMPLE, 1e-8)
+        p0, u0 = s.fields()
+        s.set_option("graphs", 1)
+        for rep in range(3):
+            r = s.solve(P.STOKES_SIMPLE, 1e-8)
+            p1, u1 = s.fields()
+            assert r["outer_iters"] == ref["outer_iters"]
+            assert r["inner_A_iters"] == ref["inner_A_iters"] and r["inner_S_iters"] == ref["inner_S_iters"]
+            assert r["k_hat"] == ref["k_hat"]
+            assert np.array_equal(p1, p0) and np.array_equal(u1, u0)
+        s.set_option("kernel_timing", 3)
+        r = s.solve(P.STOKES_SIMPLE, 1e-8)
+        assert r["k_hat"] == ref["k_hat"]
+        assert s.kernel_timing(0)[1] > 0
