@@ -8,6 +8,12 @@ p = 0 on a context whose geometry is resident in HBM (setup, which reads a
 host mask, runs once before timing and is reported separately), followed by
 the permeability read-back.
 
+Beside it, the same run serves a short seeded stream of mixed-precision
+requests (box sides 32..128, spheres or Gaussian-random-field geometries,
+Poisson arrivals at 0.8 of the measured saturated rate) through the request
+server, and reports its throughput and p50/p99 latency.  `--serve-only
+--requests 2000` runs the full serving workload alone.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 
@@ -25,6 +31,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SERVE_SLOTS = 8
+SERVE_BUDGET = 8 << 30          # HBM budget of the request server (bytes)
+
+# name: (description, side, generator)
+WORKLOADS = {
+    "spheres128": ("128^3 periodic overlapping spheres r=6 porosity 0.5 seed 0", 128,
+                   lambda: __import__("synth").spheres(128, 6.0, 0.5, 0)),
+    "tight256": ("256^3 periodic overlapping spheres r=3 porosity 0.2 seed 0", 256,
+                 lambda: __import__("synth").spheres(256, 3.0, 0.2, 0)),
+    "grf512": ("512^3 Gaussian random field corr length 8 porosity 0.15 seed 0", 512,
+               lambda: __import__("synth").grf(512, 8.0, 0.15, 0)),
+}
 
 
 def log(*a):
@@ -76,11 +94,72 @@ def cpu_baseline(mask, gpu_rep, budget_s=20.0):
     est = gpu_rep["inner_A_iters"] * tA + gpu_rep["inner_S_iters"] * tS
     return {
         "value": 1.0 / est, "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
-        "sample": (f"oracle on the same 128^3 geometry: one inner A solve ({itA} iterations, "
+        "sample": (f"oracle on the same {N}^3 geometry: one inner A solve ({itA} iterations, "
                    f"{tA * 1e3:.1f} ms each) and {itS} inner SIMPLE iterations ({tS * 1e3:.1f} ms each), "
                    f"scaled to the {gpu_rep['inner_A_iters']} + {gpu_rep['inner_S_iters']} inner iterations "
                    f"of one solve (outer-loop vector work not counted)"),
         "seconds_per_solve_est": est,
+    }
+
+
+def generate_requests(n):
+    """Masks of the first n serving requests, generated in worker processes
+    (before this process touches the GPU)."""
+    import multiprocessing as mp
+
+    from synth.requests import make_request
+    if n == 0:
+        return []
+    t0 = time.perf_counter()
+    procs = max(1, min(16, os.cpu_count() or 1, n))
+    with mp.get_context("fork").Pool(procs) as pool:
+        reqs = pool.map(make_request, range(n), chunksize=1)
+    log(f"[serve] generated {n} request geometries in {time.perf_counter() - t0:.1f} s on {procs} processes")
+    return reqs
+
+
+def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345):
+    """Saturated throughput from the whole request stream submitted at once,
+    then the same stream with Poisson arrivals at frac of that rate; latency =
+    result ready - submitted."""
+    import numpy as np
+
+    with P.Server(slots, budget) as srv:
+        t0 = srv.clock()
+        ids = [srv.submit(m, precision=1) for _, m in reqs]
+        res = [srv.wait(i) for i in ids]
+        mu = len(reqs) / (max(r["t_end"] for r in res) - t0)
+        log(f"[serve] saturated: {len(reqs)} requests in {len(reqs) / mu:.2f} s -> {mu:.2f} requests/s")
+        rate = frac * mu
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        start = time.perf_counter()
+        ids = []
+        for q, (_, m) in enumerate(reqs):
+            delay = start + arrivals[q] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(m, precision=1))
+            if (q + 1) % 100 == 0:
+                log(f"[serve] submitted {q + 1}/{len(reqs)}; {srv.stats()['completed']} done")
+        res = [srv.wait(i) for i in ids]
+        stats = srv.stats()
+    lat = np.array([r["t_end"] - r["t_submit"] for r in res])
+    span = max(r["t_end"] for r in res) - min(r["t_submit"] for r in res)
+    cells = sum(p["N"] ** 3 for p, _ in reqs)
+    bad = [r for r in res if r["status"] != 0]
+    return {
+        "requests": len(reqs), "slots": slots, "hbm_budget_GB": budget / 2 ** 30,
+        "precision": "mixed", "precond": "simple", "tol": 1e-8,
+        "saturated_requests_per_s": mu, "arrival_rate_per_s": rate, "arrival_frac": frac,
+        "throughput_requests_per_s": len(reqs) / span,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(lat.mean() * 1e3), "max": float(lat.max() * 1e3)},
+        "queue_wait_ms_p50": float(np.percentile([r["t_start"] - r["t_submit"] for r in res], 50) * 1e3),
+        "peak_running": stats["peak_running"], "peak_bytes_GB": stats["peak_bytes"] / 2 ** 30,
+        "voxels_per_s": cells / span, "failed": len(bad),
+        "workload": "seeded request stream: spheres r 2..6 or GRF corr length 4..12 (50/50), N in "
+                    "{32,48,64,96,128}, porosity 0.15..0.6, force x",
     }
 
 
@@ -89,7 +168,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--workload", default="spheres128", choices=sorted(WORKLOADS),
+                    help="geometry: the 128^3 spheres solve (default) or one of the large boxes")
     ap.add_argument("--precond", default="simple", choices=["simple", "uzawa"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--mixed-steps", type=int, default=3,
@@ -100,29 +180,44 @@ def main():
                     help="cap the outer iterations (short runs for hardware-counter profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the byte counters)")
+    ap.add_argument("--requests", type=int, default=48,
+                    help="serving requests run beside the solve benchmark (0 = skip)")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
+    ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    # one hardware queue per server slot; read when the process first uses HIP
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, args.serve_slots)))
+    reqs = generate_requests(args.requests)
 
     import torch
 
     import paper_2307_05266_amd as P
     from paper_2307_05266_amd.stokes import KERNEL_NAMES
-    from synth import spheres
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
-    N = args.N
-    log(f"[bench] generating spheres N={N} r=6 phi=0.5 seed=0")
-    mask = spheres(N, 6.0, 0.5, 0)
+    if args.serve_only:
+        sv = serve(P, reqs, slots=args.serve_slots)
+        out = {"metric": "permeability solves/s (serving)", "value": sv["throughput_requests_per_s"],
+               "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+               "dtype": "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}
+        print(json.dumps(out), flush=True)
+        return
+    desc, N, gen = WORKLOADS[args.workload]
+    log(f"[bench] generating {desc}")
+    mask = gen()
     pc = P.STOKES_SIMPLE if args.precond == "simple" else P.STOKES_UZAWA
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     s = P.Stokes(mask, (1.0, 0.0, 0.0), stream=stream.cuda_stream)
+    if N > 128:
+        s.set_option("progress", 25)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     if args.sweep_blocks:
@@ -197,7 +292,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'} {args.precond.upper()} solve, "
-                         f"{N}^3 periodic overlapping spheres r=6 porosity 0.5 seed 0, force x, tol 1e-8"),
+                         f"{desc}, force x, tol 1e-8"),
             "N": N, "precond": args.precond, "precision": args.precision, "tol": 1e-8,
         },
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
@@ -226,7 +321,8 @@ def main():
         # the same solve with FP32 inner solves and FP64 outer recurrences
         k64, div64 = rep["k_hat"], rep["div_norm"]
         s.set_option("precision", 1)
-        rm = s.solve(pc, 1e-8)  # warm-up (allocates the FP32 vectors)
+        if args.warmup > 0:
+            rm = s.solve(pc, 1e-8)  # warm-up (allocates the FP32 vectors)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.mixed_steps):
@@ -243,7 +339,11 @@ def main():
         }
         log(f"[bench] mixed: {tm:.3f} s/solve outer={rm['outer_iters']} k={rm['k_hat']:.12e}")
     s.close()
-    if not args.no_cpu_baseline:
+    if reqs:
+        out["serving"] = serve(P, reqs, slots=args.serve_slots)
+        log(f"[serve] {out['serving']['throughput_requests_per_s']:.2f} requests/s, latency p50 "
+            f"{out['serving']['latency_ms']['p50']:.0f} ms p99 {out['serving']['latency_ms']['p99']:.0f} ms")
+    if not args.no_cpu_baseline and N <= 128:
         log("[bench] timing the oracle on a bounded sample")
         cb = cpu_baseline(mask, rep)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -173,6 +173,9 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "kernel_timing" n > 0: every n-th iteration of each inner solve is launched
  *                 eagerly with each of its kernels bracketed by HIP events
  *                 (0 = off, the default); see stokes_kernel_timing
+ *   "progress"    n > 0: one line on stderr every n outer iterations
+ *                 (iteration, relative residual, permeability, elapsed
+ *                 seconds); 0 = silent (default)
  *   "graphs"      1 (default): each inner solve's iteration (CG kernels and
  *                 V-cycle) is captured once as a HIP graph and replayed; 0:
  *                 launched kernel by kernel.  Results are bitwise the same.

@@ -50,6 +50,10 @@ def _load():
         ctypes.POINTER(ctypes.c_long), ctypes.c_int
     lib.oracle_create.restype = vp
     lib.oracle_create.argtypes = [ip, ctypes.c_void_p, dp, ip]
+    lib.oracle_create_ex.restype = vp
+    lib.oracle_create_ex.argtypes = [ip, ctypes.c_void_p, dp, ip, ip]
+    lib.oracle_sample_residuals.argtypes = [vp, dp, dp, ctypes.c_long, ctypes.c_void_p, dp, ctypes.c_long,
+                                            ctypes.c_void_p, dp]
     lib.oracle_destroy.argtypes = [vp]
     lib.oracle_info.argtypes = [vp, lp]
     lib.oracle_masks.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
@@ -94,13 +98,15 @@ def lanczos_ritz(alphas, betas):
 class Oracle:
     """One geometry, assembled.  mask: uint8 (N, N, N) [k][j][i], 1 = fluid."""
 
-    def __init__(self, mask, force=(1.0, 0.0, 0.0), strip=True):
+    def __init__(self, mask, force=(1.0, 0.0, 0.0), strip=True, assemble=True):
         lib = _load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         assert mask.ndim == 3 and mask.shape[0] == mask.shape[1] == mask.shape[2]
         self.N = mask.shape[0]
         self.force = np.array(force, dtype=np.float64)
-        self._h = lib.oracle_create(self.N, mask.ctypes.data, _dptr(self.force), int(bool(strip)))
+        self.assembled = bool(assemble)
+        self._h = lib.oracle_create_ex(self.N, mask.ctypes.data, _dptr(self.force), int(bool(strip)),
+                                       int(self.assembled))
         if not self._h:
             raise ValueError("oracle_create rejected the input")
         info = np.zeros(10, dtype=np.int64)
@@ -218,3 +224,21 @@ class Oracle:
             res["ritz"] = np.zeros(0)
             res["cond_est"] = float("nan")
         return res
+
+
+def sample_residuals(orc, u, p, face_pos, cell_pos):
+    """Residual rows of the discrete Stokes system at sampled unknowns, evaluated
+    one by one from the assembly rules (no matrix is formed):
+    (A u + B^T p - f) at face positions c*N^3 + X, (B u) at cells X; NaN where
+    the position is not an unknown.  `orc` may be created with assemble=False."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    p = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
+    N = orc.N
+    assert u.size == 3 * N ** 3 and p.size == N ** 3
+    fpos = np.ascontiguousarray(face_pos, dtype=np.int64)
+    cpos = np.ascontiguousarray(cell_pos, dtype=np.int64)
+    rf = np.empty(fpos.size)
+    rc = np.empty(cpos.size)
+    _load().oracle_sample_residuals(orc._h, _dptr(u), _dptr(p), fpos.size, fpos.ctypes.data, _dptr(rf),
+                                    cpos.size, cpos.ctypes.data, _dptr(rc))
+    return rf, rc

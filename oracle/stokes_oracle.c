@@ -276,6 +276,43 @@ static void csr_push_row(csr_t *m, long row, const rowbuf_t *r)
 
 static inline int is_fluid(const osys_t *s, long X) { return s->fluid[X] != 0; }
 
+/* face (c, X) is an unknown when both of its cells are fluid */
+static inline int is_active(const osys_t *s, int c, long X)
+{
+    return is_fluid(s, X) && is_fluid(s, shift(s->N, X, c, -1));
+}
+
+/* Row of A at the active face F = c*n3 + X as (dense face position, value)
+ * pairs, the diagonal first: diagonal 6 + t, -1 for each active neighbour
+ * face (c, X +- e_d); a tangential neighbour with both cells solid is a wall
+ * half a voxel away (mirrored ghost value, +1 on the diagonal); an inactive
+ * neighbour touching fluid lies on the wall, where u = 0.  Returns the count. */
+static int a_row(const osys_t *s, long F, long *pos, double *val)
+{
+    const int N = s->N;
+    const long n3 = s->n3;
+    const int c = (int)(F / n3);
+    const long X = F % n3;
+    const long Xm = shift(N, X, c, -1);        /* the other cell of this face */
+    int n = 1;
+    double diag = 6.0;
+    for (int d = 0; d < 3; ++d) {
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long Y = shift(N, X, d, sg);         /* neighbour face (c, Y) */
+            if (is_active(s, c, Y)) {
+                pos[n] = c * n3 + Y;
+                val[n++] = -1.0;
+            } else if (d != c) {
+                long Ym = shift(N, Xm, d, sg);   /* its other cell */
+                if (!is_fluid(s, Y) && !is_fluid(s, Ym)) diag += 1.0;
+            }
+        }
+    }
+    pos[0] = F;
+    val[0] = diag;
+    return n;
+}
+
 static void assemble(osys_t *s)
 {
     const int N = s->N;
@@ -302,28 +339,14 @@ static void assemble(osys_t *s)
     csr_alloc(&s->A, s->nf, 7 * s->nf);
     s->diagA = (double *)malloc((s->nf > 0 ? s->nf : 1) * sizeof(double));
     for (long r = 0; r < s->nf; ++r) {
-        long F = s->face_pos[r];
-        int c = (int)(F / n3);
-        long X = F % n3;
-        long Xm = shift(N, X, c, -1);        /* the other cell of this face */
+        long pos[7];
+        double val[7];
+        const int n = a_row(s, s->face_pos[r], pos, val);
         rowbuf_t row;
         row.n = 0;
-        double diag = 6.0;
-        for (int d = 0; d < 3; ++d) {
-            for (int sg = -1; sg <= 1; sg += 2) {
-                long Y = shift(N, X, d, sg);         /* neighbour face (c, Y) */
-                long G = c * n3 + Y;
-                if (s->face_id[G] >= 0) {
-                    row_add(&row, s->face_id[G], -1.0);
-                } else if (d != c) {
-                    long Ym = shift(N, Xm, d, sg);   /* its other cell */
-                    if (!is_fluid(s, Y) && !is_fluid(s, Ym)) diag += 1.0;  /* wall at h/2: ghost = -u */
-                }
-                /* an inactive neighbour touching fluid sits on the wall: u = 0 there */
-            }
-        }
-        row_add(&row, r, diag);
-        s->diagA[r] = diag;
+        for (int q = 1; q < n; ++q) row_add(&row, s->face_id[pos[q]], val[q]);
+        row_add(&row, r, val[0]);
+        s->diagA[r] = val[0];
         csr_push_row(&s->A, r, &row);
     }
 
@@ -476,8 +499,10 @@ void oracle_destroy(osys_t *s)
 }
 
 /* strip = 0 keeps every fluid component (each one then carries its own
- * pressure constant); strip = 1 removes the ones that cannot conduct. */
-osys_t *oracle_create(int N, const uint8_t *mask, const double *force, int strip)
+ * pressure constant); strip = 1 removes the ones that cannot conduct.
+ * assemble = 0 stops after the components (for oracle_sample_residuals on
+ * boxes too large to assemble); every other entry point needs assemble = 1. */
+osys_t *oracle_create_ex(int N, const uint8_t *mask, const double *force, int strip, int assemble_it)
 {
     if (N < 2) return NULL;
     osys_t *s = (osys_t *)calloc(1, sizeof(osys_t));
@@ -487,14 +512,60 @@ osys_t *oracle_create(int N, const uint8_t *mask, const double *force, int strip
     s->fluid_in = (uint8_t *)malloc(s->n3);
     s->fluid = (uint8_t *)malloc(s->n3);
     s->comp = (int32_t *)malloc(s->n3 * sizeof(int32_t));
-    s->face_id = (long *)malloc(3 * s->n3 * sizeof(long));
-    s->cell_id = (long *)malloc(s->n3 * sizeof(long));
+    if (assemble_it) {
+        s->face_id = (long *)malloc(3 * s->n3 * sizeof(long));
+        s->cell_id = (long *)malloc(s->n3 * sizeof(long));
+    }
     for (long X = 0; X < s->n3; ++X) s->fluid_in[X] = mask[X] ? 1 : 0;
     count_surface(s);
     label_components(s);
     if (!strip) keep_all_components(s);
-    assemble(s);
+    if (assemble_it) assemble(s);
     return s;
+}
+
+osys_t *oracle_create(int N, const uint8_t *mask, const double *force, int strip)
+{
+    return oracle_create_ex(N, mask, force, strip, 1);
+}
+
+/* Residuals of the discrete Stokes system (Sec. 2.2) at sampled unknowns,
+ * row by row, without assembling: for the face position F = c*n3 + X,
+ *   rf = (A u)_F + p_X - p_{X-e_c} - f_c        (momentum, eq. for u)
+ * and for the cell X,
+ *   rc = -sum_c [u(c, X+e_c) - u(c, X)] over active faces   (B u, continuity).
+ * u: dense faces (3 n3), p: dense cells.  Positions that are not unknowns get
+ * NAN.  Works on a context created with or without assembly. */
+void oracle_sample_residuals(const osys_t *s, const double *u, const double *p, long nfs, const long *fpos,
+                             double *rf, long ncs, const long *cpos, double *rc)
+{
+    const int N = s->N;
+    const long n3 = s->n3;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < nfs; ++q) {
+        const long F = fpos[q];
+        const int c = (int)(F / n3);
+        const long X = F % n3;
+        if (F < 0 || F >= 3 * n3 || !is_active(s, c, X)) { rf[q] = NAN; continue; }
+        long pos[7];
+        double val[7];
+        const int n = a_row(s, F, pos, val);
+        double acc = 0.0;
+        for (int t = 0; t < n; ++t) acc += val[t] * u[pos[t]];
+        rf[q] = acc + (p[X] - p[shift(N, X, c, -1)]) - s->force[c];
+    }
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < ncs; ++q) {
+        const long X = cpos[q];
+        if (X < 0 || X >= n3 || !is_fluid(s, X)) { rc[q] = NAN; continue; }
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const long hi = shift(N, X, c, +1);
+            if (is_active(s, c, X)) acc += u[c * n3 + X];
+            if (is_active(s, c, hi)) acc -= u[c * n3 + hi];
+        }
+        rc[q] = acc;
+    }
 }
 
 /* info[0..9] = N, nfluid_in, nfluid(kept), nsurf, ncomp_all, ncomp_kept,
@@ -509,8 +580,8 @@ void oracle_info(const osys_t *s, long *info)
     info[5] = s->ncomp_kept;
     info[6] = s->nf;
     info[7] = s->nc;
-    info[8] = s->A.ptr[s->A.n];
-    info[9] = s->B.ptr[s->B.n];
+    info[8] = s->A.ptr ? s->A.ptr[s->A.n] : 0;
+    info[9] = s->B.ptr ? s->B.ptr[s->B.n] : 0;
 }
 
 /* kept fluid mask (after stripping) and kept-component labels (-1 solid) */

@@ -120,6 +120,8 @@ struct stokes_ctx {
     std::vector<void*> allocations;
     int64_t device_bytes = 0;
     bool async_alloc = false;      // allocations ordered on `stream` (stokes_setup_on_stream)
+    int progress = 0;              // > 0: report every n-th outer iteration on stderr
+    std::chrono::steady_clock::time_point t_solve0;
     CgState* host_state = nullptr; // pinned
     double* host_part = nullptr;   // pinned [3 * kMaxBlocks]
     int sweep_blocks = 1024;
@@ -1034,12 +1036,21 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         c->sw = sw;
         if (c->N % 2 == 0) c->msw = make_mg_sweep(c->N, (int)v);
     }
+    else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }
     else return STOKES_E_ARG;
     return STOKES_OK;
 }
 
 static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double tol);
+
+// one line on stderr every `progress` outer iterations (option "progress")
+static void report_progress(stokes_ctx* c, int k, double rel, double k_hat) {
+    if (c->progress <= 0 || k % c->progress != 0) return;
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - c->t_solve0).count();
+    std::fprintf(stderr, "[stokes] N=%d outer %d rel_res %.3e k_hat %.10e  %.1f s\n", c->N, k, rel, k_hat, t);
+    std::fflush(stderr);
+}
 
 static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double tol) {
     stokes_report& R = c->rep;
@@ -1160,6 +1171,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
             ST_TRY(face_sums(c, c->u, sums));
             const double kk = kvox_of(c, sums, mean) / N2;
             c->hist.insert(c->hist.end(), {rel, relz, kk, (double)(totA - a0), (double)(totS - s0), alpha, beta, 0.0});
+            report_progress(c, k, rel, kk);
             if (stop) break;
         }
     }
@@ -1337,6 +1349,7 @@ static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double t
                 const double kk = kvox_of(c, sums, mean) / N2;
                 c->hist.insert(c->hist.end(),
                                {rel, relz, kk, (double)(totA - a0), (double)(totS - s0), alpha, beta, 0.0});
+                report_progress(c, k, rel, kk);
                 if (stop) break;
             }
             if (status < 0 || status == STOKES_NOT_CONVERGED) break;
@@ -1385,6 +1398,7 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
     if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
     const auto t0 = std::chrono::steady_clock::now();
+    c->t_solve0 = t0;
     stokes_status st;
     try {
         st = solve_impl(c, precond, tol);

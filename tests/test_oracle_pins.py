@@ -465,3 +465,38 @@ def test_simple_beats_uzawa_when_tight(oracle_mod):
     ru2 = o2.solve(oracle.UZAWA, tol=1e-8)
     rs2 = o2.solve(oracle.SIMPLE, tol=1e-8)
     assert ru2["outer_iters"] <= rs2["outer_iters"]
+
+
+# --------------------------------------------------------------------------
+# Sampled residual rows (used at sizes too large to assemble): the row-by-row
+# evaluation must equal the assembled operators at every unknown, vanish on
+# the exact discrete solution, and mark non-unknowns.
+# --------------------------------------------------------------------------
+def test_sampled_residuals_match_assembled_operators(oracle_mod):
+    from synth import grf
+    rng = np.random.default_rng(3)
+    for m, force in [(spheres(12, 2.0, 0.5, 1), (1.0, 0.0, 0.0)), (grf(10, 2.0, 0.45, 2), (0.3, -1.0, 0.5))]:
+        N = m.shape[0]
+        o = oracle.Oracle(m, force)
+        light = oracle.Oracle(m, force, assemble=False)
+        u = rng.standard_normal(3 * N ** 3)
+        p = rng.standard_normal(N ** 3)
+        # dense reference from the assembled operators; inactive u entries are ignored by both
+        dA = o.apply(oracle.OP_DIAG_A, None).reshape(-1)
+        f = np.concatenate([np.full(N ** 3, force[c]) for c in range(3)]) * (dA > 0)
+        mom = o.apply(oracle.OP_A, u.reshape(3, N, N, N)).reshape(-1) + \
+            o.apply(oracle.OP_BT, p.reshape(N, N, N)).reshape(-1) - f
+        cont = o.apply(oracle.OP_B, u.reshape(3, N, N, N)).reshape(-1)
+        fpos = np.arange(3 * N ** 3)
+        cpos = np.arange(N ** 3)
+        for orc in (o, light):
+            rf, rc = oracle.sample_residuals(orc, u, p, fpos, cpos)
+            act = dA > 0
+            fl = o.masks()[0].reshape(-1) == 1
+            assert np.all(np.isnan(rf[~act])) and np.all(np.isnan(rc[~fl]))
+            assert np.allclose(rf[act], mom[act], rtol=0, atol=1e-12)
+            assert np.allclose(rc[fl], cont[fl], rtol=0, atol=1e-12)
+        # on the (tightly) solved system both residuals vanish
+        r = o.solve(oracle.SIMPLE, tol=1e-12)
+        rf, rc = oracle.sample_residuals(light, r["u"], r["p"], fpos, cpos)
+        assert np.nanmax(np.abs(rf)) < 1e-8 and np.nanmax(np.abs(rc)) < 1e-8
