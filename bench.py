@@ -51,15 +51,16 @@ def log(*a):
 
 def measured_traffic(kernel, N):
     """HBM bytes per launch of `kernel` from the committed hardware-counter summary,
-    or None when that summary was taken at another size or on other kernel code."""
+    or None when that summary was taken at another size or on other kernel code
+    (a hash of the kernel sources)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "traffic_128_spheres_inner_cg.md")
-    src = os.path.join(ROOT, "paper_2307_05266_amd", "csrc", "kernels.h")
+    srcs = [os.path.join(ROOT, "paper_2307_05266_amd", "csrc", f) for f in ("kernels.h", "mg.h")]
     try:
         m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
         table = json.loads(m.group(1))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
     except (OSError, AttributeError, ValueError):
         return None
     if table.get("kernels_sha256_16") != h or table.get("N") != N:
@@ -118,6 +119,16 @@ def generate_requests(n):
     return reqs
 
 
+def collect(srv, ids, phase):
+    """Results of the given requests, in order, with a line every 100 results."""
+    res = []
+    for q, i in enumerate(ids):
+        res.append(srv.wait(i))
+        if (q + 1) % 100 == 0 or q + 1 == len(ids):
+            log(f"[serve] {phase}: {q + 1}/{len(ids)} results at t={res[-1]['t_end']:.1f} s")
+    return res
+
+
 def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345):
     """Saturated throughput from the whole request stream submitted at once,
     then the same stream with Poisson arrivals at frac of that rate; latency =
@@ -127,7 +138,7 @@ def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345)
     with P.Server(slots, budget) as srv:
         t0 = srv.clock()
         ids = [srv.submit(m, precision=1) for _, m in reqs]
-        res = [srv.wait(i) for i in ids]
+        res = collect(srv, ids, "saturated")
         mu = len(reqs) / (max(r["t_end"] for r in res) - t0)
         log(f"[serve] saturated: {len(reqs)} requests in {len(reqs) / mu:.2f} s -> {mu:.2f} requests/s")
         rate = frac * mu
@@ -142,7 +153,7 @@ def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345)
             ids.append(srv.submit(m, precision=1))
             if (q + 1) % 100 == 0:
                 log(f"[serve] submitted {q + 1}/{len(reqs)}; {srv.stats()['completed']} done")
-        res = [srv.wait(i) for i in ids]
+        res = collect(srv, ids, "poisson")
         stats = srv.stats()
     lat = np.array([r["t_end"] - r["t_submit"] for r in res])
     span = max(r["t_end"] for r in res) - min(r["t_submit"] for r in res)

@@ -248,7 +248,9 @@ stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
  * on the context's stream.  kernel: 0 = A direction, 1 = A stencil,
  * 2 = A update, 3 = SIMPLE direction, 4 = SIMPLE stencil, 5 = SIMPLE update,
  * and the voxel-level multigrid kernels: 6 = A restriction, 7 = A smoothing,
- * 8 = SIMPLE restriction, 9 = SIMPLE smoothing.  Returns the total
+ * 8 = SIMPLE restriction, 9 = SIMPLE smoothing, 10 = A update fused with the
+ * restriction, 11 = SIMPLE update fused with the restriction (the update of
+ * the multigrid-preconditioned solves).  Returns the total
  * milliseconds and the number of timed launches (launches queued after
  * convergence return at once and are counted too), and the algorithmic bytes one launch
  * moves (each input read once, each output written once, in FP64). */

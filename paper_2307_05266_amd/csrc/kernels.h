@@ -726,6 +726,155 @@ __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restri
     }
 }
 
+// ---- LDS-tiled stencils -------------------------------------------------------
+// A block marches its BX x BY column through z; a thread keeps its own
+// column's values at k-1, k, k+1 in registers, and plane k of the tile plus a
+// one-voxel ring (loaded by the first 2 (BX + BY) threads) goes through LDS
+// (double-buffered: one barrier per plane) for the in-plane neighbours, so each
+// value is loaded from memory about once instead of seven times.  Lanes past
+// the box edge load their wrapped position, the periodic neighbour of the last
+// voxel inside.
+constexpr int kTileMax = 396;   // (BX + 2)(BY + 2): 64 x 4 -> 396, 32 x 8 -> 340
+
+struct Tile {
+    int lb, N, W;
+    int gi, gj, wi, wj;      // own column (global, wrapped)
+    bool valid;
+    int k0, k1;
+    int own;                 // LDS slot of the own column
+    bool ring;               // this thread loads a ring point
+    int hi, hj, hslot;       // its wrapped position and LDS slot
+};
+
+__device__ __forceinline__ Tile tile_of(const Sweep& s) {
+    Tile t;
+    t.N = s.N;
+    t.lb = xcd_remap((int)blockIdx.x, s.nblk);
+    const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog;
+    t.W = BX + 2;
+    const int bx = t.lb % s.gx, r = t.lb / s.gx, by = r % s.gy, bz = r / s.gy;
+    const int tx = (int)threadIdx.x & (BX - 1), ty = (int)threadIdx.x >> s.bxlog;
+    t.gi = bx * BX + tx;
+    t.gj = by * BY + ty;
+    t.valid = t.gi < s.N && t.gj < s.N;
+    t.wi = t.gi % s.N;
+    t.wj = t.gj % s.N;
+    t.k0 = bz * s.lz;
+    t.k1 = min(s.N, t.k0 + s.lz);
+    t.own = (ty + 1) * t.W + (tx + 1);
+    const int h = (int)threadIdx.x;
+    int hx, hy;
+    if (h < BY) { hx = -1; hy = h; }
+    else if (h < 2 * BY) { hx = BX; hy = h - BY; }
+    else if (h < 2 * BY + BX) { hx = h - 2 * BY; hy = -1; }
+    else { hx = h - 2 * BY - BX; hy = BY; }
+    t.ring = h < 2 * (BX + BY);
+    t.hi = ((bx * BX + hx) % s.N + s.N) % s.N;
+    t.hj = ((by * BY + hy) % s.N + s.N) % s.N;
+    t.hslot = (hy + 1) * t.W + (hx + 1);
+    return t;
+}
+
+__device__ __forceinline__ int tile_zw(int k, int N) { return k < 0 ? k + N : (k >= N ? k - N : k); }
+
+// q = Shat d on the cells and the partial (d, q), LDS-tiled
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgS_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
+                                                              const T* __restrict__ d, T* __restrict__ q,
+                                                              CgState* st, double* part) {
+    if (st->done) return;
+    __shared__ T tl[2][kTileMax];
+    const Tile t = tile_of(s);
+    const int N = t.N, N2 = N * N, W = t.W;
+    const int col = t.wi + N * t.wj;
+    const int hcol = t.hi + N * t.hj;
+    const int xp = t.wi == N - 1 ? col - (N - 1) : col + 1;
+    const int yp = t.wj == N - 1 ? col - (N - 1) * N : col + N;
+    T dprev = d[col + tile_zw(t.k0 - 1, N) * N2], dcur = d[col + t.k0 * N2];
+    int ccur = code[col + t.k0 * N2];
+    double acc[1] = {0.0};
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int kn = tile_zw(k + 1, N);
+        const T dnext = d[col + kn * N2];
+        const int cnext = code[col + kn * N2];
+        const int cxp = code[xp + k * N2], cyp = code[yp + k * N2];
+        if (t.ring) tl[buf][t.hslot] = d[hcol + k * N2];
+        tl[buf][t.own] = dcur;
+        __syncthreads();
+        const T* w = tl[buf];
+        const T qv = ((inv_diag_A_t<T>(sx_of(ccur)) * (dcur - w[t.own - 1]) +
+                       inv_diag_A_t<T>(sx_of(cxp)) * (dcur - w[t.own + 1])) +
+                      (inv_diag_A_t<T>(sy_of(ccur)) * (dcur - w[t.own - W]) +
+                       inv_diag_A_t<T>(sy_of(cyp)) * (dcur - w[t.own + W]))) +
+                     (inv_diag_A_t<T>(sz_of(ccur)) * (dcur - dprev) + inv_diag_A_t<T>(sz_of(cnext)) * (dcur - dnext));
+        if (t.valid) {
+            q[col + k * N2] = qv;
+            acc[0] += (double)dcur * (double)qv;
+        }
+        dprev = dcur;
+        dcur = dnext;
+        ccur = cnext;
+        buf ^= 1;
+    }
+    write_partials<1>(acc, part, kDQ, t.lb);
+}
+
+// q = A d on the faces (three planes) and the partial (d, q), LDS-tiled
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgA_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
+                                                              const T* __restrict__ d, T* __restrict__ q,
+                                                              CgState* st, double* part) {
+    if (st->done) return;
+    __shared__ T tl[2][3][kTileMax];
+    const Tile t = tile_of(s);
+    const int N = t.N, N2 = N * N, W = t.W;
+    const size_t n3 = (size_t)s.n3;
+    const int col = t.wi + N * t.wj;
+    const int hcol = t.hi + N * t.hj;
+    T dprev[3], dcur[3];
+    {
+        const int Xp = col + tile_zw(t.k0 - 1, N) * N2, Xc = col + t.k0 * N2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dprev[a] = d[a * n3 + Xp];
+            dcur[a] = d[a * n3 + Xc];
+        }
+    }
+    double acc[1] = {0.0};
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int Xn = col + tile_zw(k + 1, N) * N2, X = col + k * N2;
+        T dnext[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dnext[a] = d[a * n3 + Xn];
+        const int cd = code[X];
+        if (t.ring) {
+            const int Xh = hcol + k * N2;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) tl[buf][a][t.hslot] = d[a * n3 + Xh];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) tl[buf][a][t.own] = dcur[a];
+        __syncthreads();
+        const int sc[3] = {sx_of(cd), sy_of(cd), sz_of(cd)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T* w = tl[buf][a];
+            const T nbs = ((w[t.own - 1] + w[t.own + 1]) + (w[t.own - W] + w[t.own + W])) + (dprev[a] + dnext[a]);
+            const T qv = sc[a] ? (T)(5 + sc[a]) * dcur[a] - nbs : T(0);
+            if (t.valid) {
+                q[a * n3 + X] = qv;
+                acc[0] += (double)dcur[a] * (double)qv;
+            }
+            dprev[a] = dcur[a];
+            dcur[a] = dnext[a];
+        }
+        buf ^= 1;
+    }
+    write_partials<1>(acc, part, kDQ, t.lb);
+}
+
 // q = Shat d on the cells and the partial (d, q)
 template <class T>
 __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,

@@ -205,6 +205,34 @@ __device__ __forceinline__ void mg_prolong7(const MgParents& q, const T (&xp)[4]
 // ---------------------------------------------------------------------------
 constexpr int kMgTile = 396;   // (BX + 2) (BY + 2) for BX x BY = 64 x 4 (32 x 8 needs 340)
 
+// Sum of v over the 2 x 2 in-plane blocks of voxels: the i pair by shuffle
+// (lane i^1); the j pair by shuffle (lane^32) when columns are 32 wide, else
+// through LDS (64-wide columns put the two rows in different waves).  Every
+// thread of the block must call it (it may synchronise); the sums are valid in
+// the lanes of even j.  lds: NB * kBlock / 2 values.
+template <class T, int NB>
+__device__ __forceinline__ void mg_pair_sum(T (&v)[NB], int bxlog, T* lds) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) v[a] += __shfl_xor(v[a], 1, 64);
+    if (bxlog == 5) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) v[a] += __shfl_xor(v[a], 32, 64);
+        return;
+    }
+    const int tx = (int)threadIdx.x & 63, ty = (int)threadIdx.x >> 6;
+    const int slot = (ty >> 1) * 64 + tx;
+    if (ty & 1) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) lds[a * (kBlock / 2) + slot] = v[a];
+    }
+    __syncthreads();
+    if (!(ty & 1)) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) v[a] += lds[a * (kBlock / 2) + slot];
+    }
+    __syncthreads();
+}
+
 // Per-point data of the level-0 smoothed iterate.
 template <class T, int KIND>
 struct MgfPt {
@@ -241,8 +269,8 @@ __device__ __forceinline__ void mgf_point(MgfPt<T, KIND>& q, int N, int cn, int 
     }
 }
 
-// POST = false: bc = P^T (b - A x0) into level 1 (Sweep: bxlog 5, even z-runs;
-// the 2 x 2 x 2 sum uses two consecutive planes and lanes i^1, i^32).
+// POST = false: bc = P^T (b - A x0) into level 1 (Sweep with even z-runs; the
+// 2 x 2 x 2 sum adds two consecutive planes, then the 2 x 2 in-plane block).
 // POST = true: y = x' + omega D^-1 (b - A x'), nodes with 1/D = 0 held at 0,
 // and the block's partial of (b, y) into part[slot][block] (Sweep: the CG's).
 template <class T, int KIND, bool POST>
@@ -253,6 +281,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
     if (st && st->done) return;
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kMgTile];
+    __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
     const int N = s.N;
     const int lb = xcd_remap((int)blockIdx.x, s.nblk);
     const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
@@ -325,13 +354,11 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
         if (!POST && (k & 1)) {
             // pair complete: 2 x 2 in-plane sum and store
             const int cN = N >> 1;
+            mg_pair_sum<T, NB>(rsum, s.bxlog, pair_lds);
 #pragma unroll
             for (int a = 0; a < NB; ++a) {
-                T r = rsum[a];
-                r += __shfl_xor(r, 1, 64);
-                r += __shfl_xor(r, 32, 64);
                 if (valid && !(gi & 1) && !(gj & 1))
-                    out[(size_t)a * cN * cN * cN + (gi >> 1) + cN * ((gj >> 1) + cN * (k >> 1))] = r;
+                    out[(size_t)a * cN * cN * cN + (gi >> 1) + cN * ((gj >> 1) + cN * (k >> 1))] = rsum[a];
                 rsum[a] = T(0);
             }
         }
@@ -344,6 +371,142 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
         double v1[1] = {acc};
         write_partials<1>(v1, part, slot, lb);
     }
+}
+
+// The inner CG update fused with the level-0 restriction that follows it:
+// alpha from the stencil's partials, x += alpha d, rout = rin - alpha q, and
+// bc = P^T (rout - A x0), x0 = omega D^-1 rout, in one LDS-tiled sweep (the
+// updated residual is formed at every tile and ring point from rin and q).
+// rin and rout are different buffers: blocks read rin at their ring points
+// while neighbouring blocks write their own points.
+// Partials of (r, D^-1 r) and (D^-1 r, D^-1 r) go to the RZ and ZZ slots as the
+// plain update's do.  Sweep: even z-runs and the stencil's block count (its
+// partials are re-added here).
+template <class T, int KIND>
+__device__ __forceinline__ void mgf_point_upd(MgfPt<T, KIND>& q, int N, int i, int j, int k,
+                                              const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                                              const T* __restrict__ r, const T* __restrict__ qv, T alpha, T omega) {
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    const int X = i + N * (j + N * k);
+    const size_t n3 = (size_t)N * N * N;
+    q.cd = code[X];
+    if (KIND == kMgFineShat) q.inv[0] = invd[X];
+    T rv[NB], qq[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        rv[a] = r[a * n3 + X];
+        qq[a] = qv[a * n3 + X];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        if (KIND == kMgFineA) q.inv[a] = inv_diag_A_t<T>(s_plane(q.cd, a));
+        q.b[a] = rv[a] - alpha * qq[a];
+        q.x[a] = omega * q.inv[a] * q.b[a];
+    }
+}
+
+template <class T, int KIND>
+__global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const uint8_t* __restrict__ code,
+                                                                const T* __restrict__ invd, T* __restrict__ x,
+                                                                const T* __restrict__ r, T* __restrict__ rout,
+                                                                const T* __restrict__ d, const T* __restrict__ q,
+                                                                T* __restrict__ bc, T omega, CgState* st,
+                                                                double* part) {
+    if (st->done) return;
+    double alpha_d;
+    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
+    const T alpha = (T)alpha_d;
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    __shared__ T tile[2][NB][kMgTile];
+    __shared__ T pair_lds[NB * kBlock / 2];
+    const int N = s.N;
+    const size_t n3 = (size_t)s.n3;
+    const int lb = xcd_remap((int)blockIdx.x, s.nblk);
+    const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
+    const int bx = lb % s.gx, t = lb / s.gx, by = t % s.gy, bz = t / s.gy;
+    const int tx = (int)threadIdx.x & (BX - 1), ty = (int)threadIdx.x >> s.bxlog;
+    const int gi = bx * BX + tx, gj = by * BY + ty;
+    const bool valid = gi < N && gj < N;
+    const int wi = gi % N, wj = gj % N;
+    const int k0 = bz * s.lz, k1 = min(N, k0 + s.lz);
+    const int H = 2 * (BX + BY);
+    const int h = (int)threadIdx.x;
+    int hx = 0, hy = 0;
+    if (h < BY) { hx = -1; hy = h; }
+    else if (h < 2 * BY) { hx = BX; hy = h - BY; }
+    else if (h < 2 * BY + BX) { hx = h - 2 * BY; hy = -1; }
+    else { hx = h - 2 * BY - BX; hy = BY; }
+    const int hi = ((bx * BX + hx) % N + N) % N, hj = ((by * BY + hy) % N + N) % N;
+    const int hslot = (hy + 1) * W + (hx + 1);
+    const int own = (ty + 1) * W + (tx + 1);
+    auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
+
+    MgfPt<T, KIND> cur, nxt;
+    T xprev[NB];
+    {
+        MgfPt<T, KIND> pv;
+        mgf_point_upd<T, KIND>(pv, N, wi, wj, zw(k0 - 1), code, invd, r, q, alpha, omega);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
+    }
+    mgf_point_upd<T, KIND>(cur, N, wi, wj, k0, code, invd, r, q, alpha, omega);
+    double acc[2] = {0.0, 0.0};
+    T rsum[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) rsum[a] = T(0);
+    int buf = 0;
+    for (int k = k0; k < k1; ++k) {
+        mgf_point_upd<T, KIND>(nxt, N, wi, wj, zw(k + 1), code, invd, r, q, alpha, omega);
+        if (h < H) {
+            MgfPt<T, KIND> hp;
+            mgf_point_upd<T, KIND>(hp, N, hi, hj, k, code, invd, r, q, alpha, omega);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) tile[buf][a][hslot] = hp.x[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) tile[buf][a][own] = cur.x[a];
+        int cxp = 0, cyp = 0;
+        if (KIND == kMgFineShat) {
+            const int X = wi + N * (wj + N * k);
+            cxp = code[X - wi + (wi == N - 1 ? 0 : wi + 1)];
+            cyp = code[X + (wj == N - 1 ? -(N - 1) * N : N)];
+        }
+        // own point: the CG update proper
+        if (valid) {
+            const size_t X = (size_t)wi + (size_t)N * (wj + (size_t)N * k);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const size_t F = a * n3 + X;
+                x[F] = x[F] + alpha * d[F];
+                rout[F] = cur.b[a];
+                const T z = cur.b[a] * cur.inv[a];
+                acc[0] += (double)cur.b[a] * (double)z;
+                acc[1] += (double)z * (double)z;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const T* tl = tile[buf][a];
+            const T v[7] = {cur.x[a], tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev[a], nxt.x[a]};
+            rsum[a] += cur.b[a] - mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a);
+        }
+        if (k & 1) {
+            const int cN = N >> 1;
+            mg_pair_sum<T, NB>(rsum, s.bxlog, pair_lds);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                if (valid && !(gi & 1) && !(gj & 1))
+                    bc[(size_t)a * cN * cN * cN + (gi >> 1) + cN * ((gj >> 1) + cN * (k >> 1))] = rsum[a];
+                rsum[a] = T(0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = cur.x[a];
+        cur = nxt;
+        buf ^= 1;
+    }
+    write_partials<2>(acc, part, kRZ, lb);
 }
 
 // ---------------------------------------------------------------------------

@@ -47,7 +47,8 @@ constexpr int kCompBlocks = 256;
 
 // kinds of timed kernels and their algorithmic bytes per voxel (FP64)
 enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeSStencil = 4, kTimeSUpdate = 5,
-       kTimeMgARestrict = 6, kTimeMgASmooth = 7, kTimeMgSRestrict = 8, kTimeMgSSmooth = 9, kTimeKinds = 10 };
+       kTimeMgARestrict = 6, kTimeMgASmooth = 7, kTimeMgSRestrict = 8, kTimeMgSSmooth = 9,
+       kTimeAUpdRestrict = 10, kTimeSUpdRestrict = 11, kTimeKinds = 12 };
 // A dir     : r, d read (3 planes each), code byte read; d written
 // A stencil : d read, code byte read; q written
 // A update  : x, d, r, q read, code byte read; x, r written
@@ -59,9 +60,11 @@ enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeS
 // A smoothing     : b (3 planes), code byte, level-1 x read; y (3 planes) written
 // S restriction   : b, inverse diagonal, code byte read; level-1 b written
 // S smoothing     : b, inverse diagonal, code byte, level-1 x read; y written
-constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,    6 * 8 + 1,         18 * 8 + 1,   4 * 8,    2 * 8 + 1,
-                                              7 * 8,        3 * 8 + 1 + 3,     6 * 8 + 1 + 3, 2 * 8 + 1 + 1,
-                                              3 * 8 + 1 + 1};
+// A update + restriction: x, r, d, q read (3 planes), code byte; x, r written, level-1 b written
+// S update + restriction: inverse diagonal, x, r, d, q read, code byte; x, r written, level-1 b written
+constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,     6 * 8 + 1,         18 * 8 + 1,    4 * 8,
+                                              2 * 8 + 1,     7 * 8,             3 * 8 + 1 + 3, 6 * 8 + 1 + 3,
+                                              2 * 8 + 1 + 1, 3 * 8 + 1 + 1,     18 * 8 + 1 + 3, 7 * 8 + 1 + 1};
 
 }  // namespace
 
@@ -107,13 +110,14 @@ struct stokes_ctx {
         std::vector<Lev32> l32;
         double* z = nullptr;           // fine level: output of the cycle
         float* z32 = nullptr;
+        double* r2 = nullptr;          // fine level: second residual buffer of the fused update
+        float* r2_32 = nullptr;
     };
     MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
     int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
     double mg_omega = 0.8, mg_scale = 1.6;
     int mg_coarse_sweeps = 16;
-    Sweep msw{};                       // level-0 restriction sweep (even N)
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -177,25 +181,8 @@ Sweep make_sweep(int N, int target_blocks) {
     const int cols = s.gx * s.gy;
     int gz = std::max(1, std::min(N, (target_blocks + cols - 1) / cols));
     s.lz = (N + gz - 1) / gz;
-    s.gz = (N + s.lz - 1) / s.lz;
-    s.nblk = s.gx * s.gy * s.gz;
-    return s;
-}
-
-// Sweep of the level-0 restriction: 32 x 8 columns (a wave holds 2 x 2 voxel
-// blocks in lanes i^1 and i^32) and an even run of z-planes per block.
-// N must be even.
-Sweep make_mg_sweep(int N, int target_blocks) {
-    Sweep s{};
-    s.N = N;
-    s.N2 = N * N;
-    s.n3 = N * N * N;
-    s.bxlog = 5;
-    s.gx = (N + 31) / 32;
-    s.gy = (N + 7) / 8;
-    const int cols = s.gx * s.gy;
-    const int gz = std::max(1, std::min(N / 2, (target_blocks + cols - 1) / cols));
-    s.lz = 2 * ((N / 2 + gz - 1) / gz);
+    // even N: even z-runs, so the multigrid restriction pairs planes within a block
+    if (N % 2 == 0 && (s.lz & 1)) ++s.lz;
     s.gz = (N + s.lz - 1) / s.lz;
     s.nblk = s.gx * s.gy * s.gz;
     return s;
@@ -337,29 +324,36 @@ stokes_status capture_graph(stokes_ctx* c, Body& body, hipGraphExec_t* out) {
 }
 
 // Run inner-CG iterations of solve `which` (0: A, 1: SIMPLE) until the device
-// state says done.  key identifies the launch sequence (solver variant and the
-// vectors it touches) for the graph cache.
+// state says done.  body(parity) launches one iteration; iterations go in
+// pairs (parity 0 then 1: the fused multigrid update alternates its two
+// residual buffers), so a graph holds one pair and a batch is rounded up to
+// whole pairs (iterations queued after convergence return at once).  key
+// identifies the launch sequence (solver variant and vectors) for the cache.
 template <class Body>
 stokes_status run_inner(stokes_ctx* c, int which, const GraphKey& key, Body body, int* iters, int* status) {
+    auto pair = [&body]() -> stokes_status {
+        ST_TRY(body(0));
+        return body(1);
+    };
     hipGraphExec_t g = nullptr;
     if (c->use_graphs) {
         auto it = c->graphs.find(key);
         if (it != c->graphs.end()) {
             g = it->second;
         } else {
-            ST_TRY(capture_graph(c, body, &g));
+            ST_TRY(capture_graph(c, pair, &g));
             c->graphs[key] = g;
         }
     }
     int batch = first_batch(c, which);
     CgState h{};
     for (;;) {
-        for (int t = 0; t < batch; ++t) {
+        for (int t = 0; t < (batch + 1) / 2; ++t) {
             c->time_iter = c->timing && (c->timing_seen[which]++ % c->timing) == 0;
             if (g && !c->time_iter) {
                 HIP_TRY(hipGraphLaunch(g, c->stream));
             } else {
-                ST_TRY(body());
+                ST_TRY(pair());
             }
             c->time_iter = false;
         }
@@ -391,14 +385,14 @@ stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int*
     hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
                        c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
-    auto body = [c, s, st, v]() -> stokes_status {
+    auto body = [c, s, st, v](int) -> stokes_status {
         bool open;
         ST_TRY(time_begin(c, kTimeADir, &open));
         hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st, c->part,
                            (const T*)nullptr);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeAStencil, &open));
-        hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+        hipLaunchKernelGGL(k_cgA_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                            c->part);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeAUpdate, &open));
@@ -423,14 +417,14 @@ stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int*
     hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
-    auto body = [c, s, st, v]() -> stokes_status {
+    auto body = [c, s, st, v](int) -> stokes_status {
         bool open;
         ST_TRY(time_begin(c, kTimeSDir, &open));
         hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st, c->part,
                            (const T*)nullptr);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeSStencil, &open));
-        hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+        hipLaunchKernelGGL(k_cgS_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                            c->part);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeSUpdate, &open));
@@ -482,6 +476,7 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
         for (double** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, m));
     }
     ST_TRY(dev_alloc(c, &h.z, (size_t)nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.r2, (size_t)nb * c->n3));
     const int m1 = nb * h.grid[1].n3;
     hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
                        h.grid[0], h.grid[1], kind, c->code, h.l64[1].D, h.l64[1].Wx, h.l64[1].Wy, h.l64[1].Wz);
@@ -513,6 +508,7 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
             hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m)), dim3(kBlock), 0, c->stream, m, src[q], dst[q]);
     }
     ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.r2_32, (size_t)h.nb * c->n3));
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -531,11 +527,14 @@ MgView<float> mg_view(MgHier& h, int l, float) {
 }
 double* mg_out(MgHier& h, double) { return h.z; }
 float* mg_out(MgHier& h, float) { return h.z32; }
+double* mg_r2(MgHier& h, double) { return h.r2; }
+float* mg_r2(MgHier& h, float) { return h.r2_32; }
 
 // z0 = V-cycle applied to the fine residual b0; the last fine sweep writes the
 // partials of (b0, z0) into the RZ slot of the CG loop (grid = the CG sweeps').
 template <class T>
-stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st) {
+stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st,
+                     bool restricted = false) {
     const int L = h.levels;
     const T omega = (T)c->mg_omega, scale = (T)c->mg_scale;
     std::vector<MgOp> ops(L + 1);
@@ -546,18 +545,19 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     }
     auto nodes = [&](int l) { return h.nb * h.grid[l].n3; };
     const bool kindA = h.kind == kMgFineA;
-    // descend: residual of the first Jacobi sweep, restricted
-    {
+    // descend: residual of the first Jacobi sweep, restricted (unless the
+    // fused CG update already did)
+    if (!restricted) {
         const MgGrid& cg = h.grid[1];
         T* bc = mg_view(h, 1, T()).b;
         bool open;
         ST_TRY(time_begin(c, kindA ? kTimeMgARestrict : kTimeMgSRestrict, &open));
         if (kindA)
-            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, false>), grid_of(c->msw), dim3(kBlock), 0, c->stream,
-                               c->msw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, false>), grid_of(c->sw), dim3(kBlock), 0, c->stream,
+                               c->sw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         else
-            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, false>), grid_of(c->msw), dim3(kBlock), 0, c->stream,
-                               c->msw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, false>), grid_of(c->sw), dim3(kBlock), 0, c->stream,
+                               c->sw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         ST_TRY(time_end(c, open));
     }
     for (int l = 1; l < L; ++l)
@@ -603,21 +603,29 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
                        eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     ST_TRY(vcycle<T>(c, c->mgS, v.r, v.invd, z, nullptr));
-    auto body = [c, s, st, v, z]() -> stokes_status {
+    // the fused update's 2x2x2 sums pair planes within a block
+    if ((s.lz & 1) || (s.bxlog != 5 && s.bxlog != 6)) return STOKES_E_LIMIT;
+    T* r2 = mg_r2(c->mgS, T());
+    T* bc = mg_view(c->mgS, 1, T()).b;
+    const T omega = (T)c->mg_omega;
+    auto body = [c, s, st, v, z, r2, bc, omega](int parity) -> stokes_status {
+        T* rin = parity ? r2 : v.r;
+        T* rout = parity ? v.r : r2;
         bool open;
         ST_TRY(time_begin(c, kTimeSDir, &open));
-        hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.r, v.d, st, c->part,
+        hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, rin, v.d, st, c->part,
                            (const T*)z);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeSStencil, &open));
-        hipLaunchKernelGGL(k_cgS_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+        hipLaunchKernelGGL(k_cgS_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                            c->part);
         ST_TRY(time_end(c, open));
-        ST_TRY(time_begin(c, kTimeSUpdate, &open));
-        hipLaunchKernelGGL(k_cgS_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, v.x, v.r, v.d, v.q,
-                           st, c->part);
+        ST_TRY(time_begin(c, kTimeSUpdRestrict, &open));
+        hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineShat>), grid_of(s), dim3(kBlock), 0, c->stream, s,
+                           c->code, v.invd, v.x, (const T*)rin, rout, (const T*)v.d, (const T*)v.q, bc, omega, st,
+                           c->part);
         ST_TRY(time_end(c, open));
-        return vcycle<T>(c, c->mgS, v.r, v.invd, z, st);
+        return vcycle<T>(c, c->mgS, rout, v.invd, z, st, true);
     };
     return run_inner(c, 1, graph_key<T>(2, v.x, v.r, v.d, v.q, v.invd, z), body, iters, status);
 }
@@ -633,21 +641,29 @@ stokes_status cg_A_mg(stokes_ctx* c, InnerA<T> v, const double* b, double eps, i
                        c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
     HIP_TRY(hipGetLastError());
     ST_TRY(vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, nullptr));
-    auto body = [c, s, st, v, z]() -> stokes_status {
+    // the fused update's 2x2x2 sums pair planes within a block
+    if ((s.lz & 1) || (s.bxlog != 5 && s.bxlog != 6)) return STOKES_E_LIMIT;
+    T* r2 = mg_r2(c->mgA, T());
+    T* bc = mg_view(c->mgA, 1, T()).b;
+    const T omega = (T)c->mg_omega;
+    auto body = [c, s, st, v, z, r2, bc, omega](int parity) -> stokes_status {
+        T* rin = parity ? r2 : v.r;
+        T* rout = parity ? v.r : r2;
         bool open;
         ST_TRY(time_begin(c, kTimeADir, &open));
-        hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.r, v.d, st, c->part,
+        hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, rin, v.d, st, c->part,
                            (const T*)z);
         ST_TRY(time_end(c, open));
         ST_TRY(time_begin(c, kTimeAStencil, &open));
-        hipLaunchKernelGGL(k_cgA_stencil<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
+        hipLaunchKernelGGL(k_cgA_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
                            c->part);
         ST_TRY(time_end(c, open));
-        ST_TRY(time_begin(c, kTimeAUpdate, &open));
-        hipLaunchKernelGGL(k_cgA_update<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.x, v.r, v.d, v.q,
-                           st, c->part);
+        ST_TRY(time_begin(c, kTimeAUpdRestrict, &open));
+        hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineA>), grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                           (const T*)nullptr, v.x, (const T*)rin, rout, (const T*)v.d, (const T*)v.q, bc, omega, st,
+                           c->part);
         ST_TRY(time_end(c, open));
-        return vcycle<T>(c, c->mgA, v.r, (const T*)nullptr, z, st);
+        return vcycle<T>(c, c->mgA, rout, (const T*)nullptr, z, st, true);
     };
     return run_inner(c, 0, graph_key<T>(3, v.x, v.r, v.d, v.q, nullptr, z), body, iters, status);
 }
@@ -800,9 +816,10 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
 
     const int N = c->N;
     const int64_t n3 = c->n3;
+    // one sweep for every kernel (the fused update and restriction re-adds the
+    // stencil's partials, so both need one block count)
     c->sw = make_sweep(N, c->sweep_blocks);
     if (c->sw.nblk > kMaxBlocks) return STOKES_E_LIMIT;
-    if (N % 2 == 0) c->msw = make_mg_sweep(N, c->sweep_blocks);
     c->wpr = (N + 31) / 32;
 
     // remaining-fluid bitmask
@@ -966,7 +983,7 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
         for (int prec = 0; prec <= precision; ++prec) {
             const int64_t w = prec == 0 ? 8 : 4;
             for (size_t l = 1; l < ns.size(); ++l) t += 7 * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
-            t += blk(nb * n3, w);   // cycle output on level 0
+            t += 2 * blk(nb * n3, w);   // cycle output and second residual on level 0
         }
     }
     if (precision == 1) t += 4 * blk(3 * n3, 4) + 5 * blk(n3, 4);
@@ -1034,7 +1051,6 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         if (sw.nblk > kMaxBlocks) return STOKES_E_ARG;
         c->sweep_blocks = (int)v;
         c->sw = sw;
-        if (c->N % 2 == 0) c->msw = make_mg_sweep(c->N, (int)v);
     }
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }

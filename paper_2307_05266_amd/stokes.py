@@ -246,9 +246,9 @@ def stokes_info(ctx):
     return {k: int(info[i]) for i, k in enumerate(keys)}
 
 
-KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil", "k_cgS_update",
+KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil_tiled", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil_tiled", "k_cgS_update",
                 "k_mgf_tiled<A,restrict>", "k_mgf_tiled<A,smooth>", "k_mgf_tiled<S,restrict>",
-                "k_mgf_tiled<S,smooth>"]
+                "k_mgf_tiled<S,smooth>", "k_mgf_update_restrict<A>", "k_mgf_update_restrict<S>"]
 
 
 def stokes_kernel_timing(ctx, kernel):

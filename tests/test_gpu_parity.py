@@ -373,20 +373,26 @@ def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
 
 
 def test_kernel_timing_counts_every_kind(P):
-    """Sampled HIP-event timing covers the six CG kernels and the four voxel-level
-    multigrid kernels; bytes per launch follow the per-voxel byte model."""
+    """Sampled HIP-event timing covers every kernel the inner solves launch:
+    with multigrid the direction, stencil, fused update + restriction and
+    level-0 smoothing kernels; with Jacobi the direction, stencil and update
+    kernels.  Bytes per launch follow the per-voxel byte model."""
     from paper_2307_05266_amd.stokes import KERNEL_NAMES
     N = 32
-    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26]
+    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26, 148, 58]
+    assert len(KERNEL_NAMES) == len(per_voxel)
     with P.Stokes(spheres(N, 3.0, 0.5, 1)) as s:
-        s.set_option("kernel_timing", 1)
-        s.solve(P.STOKES_SIMPLE, 1e-8)
-        for kind, name in enumerate(KERNEL_NAMES):
-            ms, n, nbytes = s.kernel_timing(kind)
-            say(f"    {name}: {n} launches {ms:.3f} ms")
-            assert n > 0 and ms > 0.0, name
-            assert nbytes == per_voxel[kind] * N ** 3
-            assert s.kernel_timing(kind)[1] == 0   # reset by the read
+        for mg, launched in [(1, {0, 1, 3, 4, 7, 9, 10, 11}), (0, {0, 1, 2, 3, 4, 5})]:
+            s.set_option("mg", mg)
+            s.set_option("mg_A", mg)
+            s.set_option("kernel_timing", 1)
+            s.solve(P.STOKES_SIMPLE, 1e-8)
+            for kind, name in enumerate(KERNEL_NAMES):
+                ms, n, nbytes = s.kernel_timing(kind)
+                say(f"    mg={mg} {name}: {n} launches {ms:.3f} ms")
+                assert (n > 0 and ms > 0.0) == (kind in launched), name
+                assert nbytes == per_voxel[kind] * N ** 3
+                assert s.kernel_timing(kind)[1] == 0   # reset by the read
         with pytest.raises(P.StokesError):
             s.kernel_timing(len(KERNEL_NAMES))
 
