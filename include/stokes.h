@@ -187,7 +187,7 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 paper gives to algebraic multigrid (Sec. 3.2); 0: Jacobi.
  *                 The inner stopping test is the same either way.
  *   "mg_omega", "mg_scale", "mg_coarse_sweeps"  V-cycle smoothing weight
- *                 (0.8), coarse-correction scale (1.6, below 2 keeps it SPD),
+ *                 (0.9), coarse-correction scale (1.7, below 2 keeps it SPD),
  *                 coarsest-level sweeps (16)
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated

@@ -605,6 +605,122 @@ __global__ void k_mgc_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, con
     y[I] = m.inv[0] > T(0) ? v[0] + omega * m.inv[0] * (m.b[0] - ax) : T(0);
 }
 
+// Levels >= 1 with a side of at least 32, LDS-tiled like level 0: the
+// smoothed iterate (x0 = omega D^-1 b, plus scale P xc when smoothing) once per
+// point, own column k-1, k, k+1 in registers, plane k plus a ring in LDS.  The
+// couplings to +x and +y are read from the neighbour's W^x, W^y; the one to +z
+// is the next plane's own W^z.  s: a sweep over this level (even z-runs).
+template <class T, int NB>
+struct MgcPt {
+    T d[NB], b[NB], x[NB], wz[NB];
+};
+
+template <class T, int NB, bool POST>
+__device__ __forceinline__ void mgc_point(MgcPt<T, NB>& q, int n, int cn, int i, int j, int k, const MgOp& op,
+                                          const T* __restrict__ b, const T* __restrict__ xc, T scale, T omega) {
+    const size_t n3 = (size_t)n * n * n;
+    const int X = i + n * (j + n * k);
+    const T* D = (const T*)op.D;
+    const T* Wz = (const T*)op.Wz;
+    T e[NB];
+    if (POST) {
+        const size_t cn3 = (size_t)cn * cn * cn;
+        const int C = (i >> 1) + cn * ((j >> 1) + cn * (k >> 1));
+#pragma unroll
+        for (int a = 0; a < NB; ++a) e[a] = xc[a * cn3 + C];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        q.d[a] = D[a * n3 + X];
+        q.b[a] = b[a * n3 + X];
+        q.wz[a] = Wz[a * n3 + X];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const T inv = q.d[a] > T(0) ? T(1) / q.d[a] : T(0);
+        q.x[a] = omega * inv * q.b[a];
+        if (POST) q.x[a] += scale * e[a];
+    }
+}
+
+template <class T, int NB, bool POST>
+__global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, const T* __restrict__ b,
+                                                      const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
+                                                      const CgState* st) {
+    if (st && st->done) return;
+    __shared__ T tile[2][NB][kMgTile];
+    __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
+    const Tile t = tile_of(s);
+    const int n = t.N, W = t.W;
+    const size_t n3 = (size_t)s.n3;
+    const T* Wx = (const T*)op.Wx;
+    const T* Wy = (const T*)op.Wy;
+    auto zw = [n](int k) { return k < 0 ? k + n : (k >= n ? k - n : k); };
+    MgcPt<T, NB> cur, nxt;
+    T xprev[NB];
+    {
+        MgcPt<T, NB> pv;
+        mgc_point<T, NB, POST>(pv, n, cn, t.wi, t.wj, zw(t.k0 - 1), op, b, xc, scale, omega);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
+    }
+    mgc_point<T, NB, POST>(cur, n, cn, t.wi, t.wj, t.k0, op, b, xc, scale, omega);
+    T rsum[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) rsum[a] = T(0);
+    const int xp = t.wi == n - 1 ? 0 : t.wi + 1, yp = t.wj == n - 1 ? 0 : t.wj + 1;
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        mgc_point<T, NB, POST>(nxt, n, cn, t.wi, t.wj, zw(k + 1), op, b, xc, scale, omega);
+        if (t.ring) {
+            MgcPt<T, NB> hp;
+            mgc_point<T, NB, POST>(hp, n, cn, t.hi, t.hj, k, op, b, xc, scale, omega);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) tile[buf][a][t.hslot] = hp.x[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) tile[buf][a][t.own] = cur.x[a];
+        const int X = t.wi + n * (t.wj + n * k);
+        const int Xxp = xp + n * (t.wj + n * k), Xyp = t.wi + n * (yp + n * k);
+        T wx[NB], wxp[NB], wy[NB], wyp[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            wx[a] = Wx[a * n3 + X];
+            wxp[a] = Wx[a * n3 + Xxp];
+            wy[a] = Wy[a * n3 + X];
+            wyp[a] = Wy[a * n3 + Xyp];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const T* tl = tile[buf][a];
+            const T ax = cur.d[a] * cur.x[a] - (((wx[a] * tl[t.own - 1] + wxp[a] * tl[t.own + 1]) +
+                                                 (wy[a] * tl[t.own - W] + wyp[a] * tl[t.own + W])) +
+                                                (cur.wz[a] * xprev[a] + nxt.wz[a] * nxt.x[a]));
+            if (POST) {
+                const T inv = cur.d[a] > T(0) ? T(1) / cur.d[a] : T(0);
+                if (t.valid) out[a * n3 + X] = inv > T(0) ? cur.x[a] + omega * inv * (cur.b[a] - ax) : T(0);
+            } else {
+                rsum[a] += cur.b[a] - ax;
+            }
+        }
+        if (!POST && (k & 1)) {
+            mg_pair_sum<T, NB>(rsum, s.bxlog, pair_lds);
+            const size_t cn3 = (size_t)cn * cn * cn;
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                if (t.valid && !(t.gi & 1) && !(t.gj & 1))
+                    out[a * cn3 + (t.gi >> 1) + cn * ((t.gj >> 1) + cn * (k >> 1))] = rsum[a];
+                rsum[a] = T(0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a) xprev[a] = cur.x[a];
+        cur = nxt;
+        buf ^= 1;
+    }
+}
+
 // Coarsest level: `sweeps` damped-Jacobi sweeps from zero inside one workgroup
 // (x in LDS, double-buffered).  Each thread keeps the coefficients and
 // neighbour indices of its nodes in registers, so a sweep touches only LDS.

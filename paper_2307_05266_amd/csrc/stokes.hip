@@ -104,6 +104,7 @@ struct stokes_ctx {
         int levels = 0;                // 0: none (odd size or tiny box)
         int nb = 1, kind = 0;
         std::vector<MgGrid> grid;      // [0..levels]
+        std::vector<Sweep> sweep;      // [0..levels]: sweeps of the tiled level kernels (side >= 64)
         struct Lev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y; };
         struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y; };
         std::vector<Lev64> l64;        // [1..levels]
@@ -116,7 +117,7 @@ struct stokes_ctx {
     MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
     int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
-    double mg_omega = 0.8, mg_scale = 1.6;
+    double mg_omega = 0.9, mg_scale = 1.7;
     int mg_coarse_sweeps = 16;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
@@ -448,6 +449,12 @@ using MgHier = stokes_ctx::MgHier;
 
 // Levels: halve while the side is even and a level holds more than 512 nodes
 // per plane; the coarsest level must fit one workgroup's LDS.
+// Coarse levels with a side of at least this run the LDS-tiled kernels (over a
+// sweep of about kMgLevelBlocks blocks); smaller ones are launch-latency bound
+// and keep one thread per node.
+constexpr int kMgTiledMinSide = 64;
+constexpr int kMgLevelBlocks = 256;
+
 // Sides of the levels of a hierarchy with nb planes on an N^3 box (level 0
 // first); a single entry when there is no hierarchy.
 std::vector<int> mg_plan(int N, int nb) {
@@ -466,7 +473,11 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     h.nb = nb;
     h.kind = kind;
     h.grid.clear();
-    for (int n : mg_plan(c->N, nb)) h.grid.push_back({n, n * n, n * n * n, nb});
+    h.sweep.clear();
+    for (int n : mg_plan(c->N, nb)) {
+        h.grid.push_back({n, n * n, n * n * n, nb});
+        h.sweep.push_back(make_sweep(n, kMgLevelBlocks));
+    }
     const int L = (int)h.grid.size() - 1;
     if (L < 1) return STOKES_OK;
     h.l64.assign(L + 1, {});
@@ -560,10 +571,22 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
                                c->sw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         ST_TRY(time_end(c, open));
     }
-    for (int l = 1; l < L; ++l)
-        hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0, c->stream,
-                           h.grid[l], h.grid[l + 1], ops[l], (const T*)mg_view(h, l, T()).b, mg_view(h, l + 1, T()).b,
-                           omega, st);
+    for (int l = 1; l < L; ++l) {
+        const T* bl = mg_view(h, l, T()).b;
+        T* bn = mg_view(h, l + 1, T()).b;
+        if (h.grid[l].n >= kMgTiledMinSide) {
+            const Sweep& ls = h.sweep[l];
+            if (kindA)
+                hipLaunchKernelGGL((k_mgc_tiled<T, 3, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
+            else
+                hipLaunchKernelGGL((k_mgc_tiled<T, 1, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
+        } else {
+            hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0,
+                               c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
+        }
+    }
     // coarsest: Jacobi sweeps in one workgroup, result in x
     {
         auto v = mg_view(h, L, T());
@@ -575,8 +598,19 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     auto coarse_x = [&](int l) -> const T* { return l == L ? mg_view(h, L, T()).x : mg_view(h, l, T()).y; };
     for (int l = L - 1; l >= 1; --l) {
         auto v = mg_view(h, l, T());
-        hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream, h.grid[l],
-                           ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y, st);
+        if (h.grid[l].n >= kMgTiledMinSide) {
+            const Sweep& ls = h.sweep[l];
+            if (kindA)
+                hipLaunchKernelGGL((k_mgc_tiled<T, 3, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
+            else
+                hipLaunchKernelGGL((k_mgc_tiled<T, 1, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
+        } else {
+            hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream,
+                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y,
+                               st);
+        }
     }
     bool open;
     ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : kTimeMgSSmooth, &open));
