@@ -143,14 +143,15 @@ struct MgOp {
 // KIND Shat: sum over the six faces of w (x_X - x_nbr), w = 1 / diag(A) of
 // the face (0 on an inactive face).
 template <class T, int KIND>
-__device__ __forceinline__ T mgf_apply(const T (&v)[7], int cX, int cxp, int cyp, int czp, int a) {
+__device__ __forceinline__ T mgf_apply(const T (&v)[7], int cX, int cxp, int cyp, int czp, int a,
+                                       const FaceTab<T>& ft) {
     if (KIND == kMgFineA) {
-        const int sc = s_plane(cX, a);
+        const T dg = ft.dg[a][cX];
         const T nb = ((v[1] + v[2]) + (v[3] + v[4])) + (v[5] + v[6]);
-        return sc ? (T)(5 + sc) * v[0] - nb : T(0);
+        return dg > T(0) ? dg * v[0] - nb : T(0);
     }
-    const T wxl = inv_diag_A_t<T>(sx_of(cX)), wyl = inv_diag_A_t<T>(sy_of(cX)), wzl = inv_diag_A_t<T>(sz_of(cX));
-    const T wxh = inv_diag_A_t<T>(sx_of(cxp)), wyh = inv_diag_A_t<T>(sy_of(cyp)), wzh = inv_diag_A_t<T>(sz_of(czp));
+    const T wxl = ft.inv[0][cX], wyl = ft.inv[1][cX], wzl = ft.inv[2][cX];
+    const T wxh = ft.inv[0][cxp], wyh = ft.inv[1][cyp], wzh = ft.inv[2][czp];
     return ((wxl * (v[0] - v[1]) + wxh * (v[0] - v[2])) + (wyl * (v[0] - v[3]) + wyh * (v[0] - v[4]))) +
            (wzl * (v[0] - v[5]) + wzh * (v[0] - v[6]));
 }
@@ -246,7 +247,8 @@ struct MgfPt {
 template <class T, int KIND, bool POST>
 __device__ __forceinline__ void mgf_point(MgfPt<T, KIND>& q, int N, int cn, int i, int j, int k,
                                           const uint8_t* __restrict__ code, const T* __restrict__ invd,
-                                          const T* __restrict__ b, const T* __restrict__ xc, T scale, T omega) {
+                                          const T* __restrict__ b, const T* __restrict__ xc, T scale, T omega,
+                                          const FaceTab<T>& ft) {
     constexpr int NB = MgfPt<T, KIND>::NB;
     const int X = i + N * (j + N * k);
     const size_t n3 = (size_t)N * N * N;
@@ -263,7 +265,7 @@ __device__ __forceinline__ void mgf_point(MgfPt<T, KIND>& q, int N, int cn, int 
     for (int a = 0; a < NB; ++a) q.b[a] = b[a * n3 + X];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-        if (KIND == kMgFineA) q.inv[a] = inv_diag_A_t<T>(s_plane(q.cd, a));
+        if (KIND == kMgFineA) q.inv[a] = ft.inv[a][q.cd];
         q.x[a] = omega * q.inv[a] * q.b[a];
         if (POST) q.x[a] += scale * e[a];
     }
@@ -282,6 +284,9 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kMgTile];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    __syncthreads();
     const int N = s.N;
     const int lb = xcd_remap((int)blockIdx.x, s.nblk);
     const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
@@ -308,21 +313,21 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
     T xprev[NB];
     {
         MgfPt<T, KIND> pv;
-        mgf_point<T, KIND, POST>(pv, N, cn, wi, wj, zw(k0 - 1), code, invd, b, xc, scale, omega);
+        mgf_point<T, KIND, POST>(pv, N, cn, wi, wj, zw(k0 - 1), code, invd, b, xc, scale, omega, ft);
 #pragma unroll
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
-    mgf_point<T, KIND, POST>(cur, N, cn, wi, wj, k0, code, invd, b, xc, scale, omega);
+    mgf_point<T, KIND, POST>(cur, N, cn, wi, wj, k0, code, invd, b, xc, scale, omega, ft);
     double acc = 0.0;       // POST: partial of (b, y)
     T rsum[NB];             // restriction: residual summed over the plane pair
 #pragma unroll
     for (int a = 0; a < NB; ++a) rsum[a] = T(0);
     int buf = 0;
     for (int k = k0; k < k1; ++k) {
-        mgf_point<T, KIND, POST>(nxt, N, cn, wi, wj, zw(k + 1), code, invd, b, xc, scale, omega);
+        mgf_point<T, KIND, POST>(nxt, N, cn, wi, wj, zw(k + 1), code, invd, b, xc, scale, omega, ft);
         if (h < H) {
             MgfPt<T, KIND> hp;
-            mgf_point<T, KIND, POST>(hp, N, cn, hi, hj, k, code, invd, b, xc, scale, omega);
+            mgf_point<T, KIND, POST>(hp, N, cn, hi, hj, k, code, invd, b, xc, scale, omega, ft);
 #pragma unroll
             for (int a = 0; a < NB; ++a) tile[buf][a][hslot] = hp.x[a];
         }
@@ -340,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
         for (int a = 0; a < NB; ++a) {
             const T* tl = tile[buf][a];
             const T v[7] = {cur.x[a], tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev[a], nxt.x[a]};
-            const T ax = mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a);
+            const T ax = mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a, ft);
             if (POST) {
                 const T yv = cur.inv[a] > T(0) ? v[0] + omega * cur.inv[a] * (cur.b[a] - ax) : T(0);
                 if (valid) {
@@ -385,7 +390,8 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
 template <class T, int KIND>
 __device__ __forceinline__ void mgf_point_upd(MgfPt<T, KIND>& q, int N, int i, int j, int k,
                                               const uint8_t* __restrict__ code, const T* __restrict__ invd,
-                                              const T* __restrict__ r, const T* __restrict__ qv, T alpha, T omega) {
+                                              const T* __restrict__ r, const T* __restrict__ qv, T alpha, T omega,
+                                              const FaceTab<T>& ft) {
     constexpr int NB = MgfPt<T, KIND>::NB;
     const int X = i + N * (j + N * k);
     const size_t n3 = (size_t)N * N * N;
@@ -399,7 +405,7 @@ __device__ __forceinline__ void mgf_point_upd(MgfPt<T, KIND>& q, int N, int i, i
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-        if (KIND == kMgFineA) q.inv[a] = inv_diag_A_t<T>(s_plane(q.cd, a));
+        if (KIND == kMgFineA) q.inv[a] = ft.inv[a][q.cd];
         q.b[a] = rv[a] - alpha * qq[a];
         q.x[a] = omega * q.inv[a] * q.b[a];
     }
@@ -419,6 +425,9 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kMgTile];
     __shared__ T pair_lds[NB * kBlock / 2];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    __syncthreads();
     const int N = s.N;
     const size_t n3 = (size_t)s.n3;
     const int lb = xcd_remap((int)blockIdx.x, s.nblk);
@@ -445,21 +454,21 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
     T xprev[NB];
     {
         MgfPt<T, KIND> pv;
-        mgf_point_upd<T, KIND>(pv, N, wi, wj, zw(k0 - 1), code, invd, r, q, alpha, omega);
+        mgf_point_upd<T, KIND>(pv, N, wi, wj, zw(k0 - 1), code, invd, r, q, alpha, omega, ft);
 #pragma unroll
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
-    mgf_point_upd<T, KIND>(cur, N, wi, wj, k0, code, invd, r, q, alpha, omega);
+    mgf_point_upd<T, KIND>(cur, N, wi, wj, k0, code, invd, r, q, alpha, omega, ft);
     double acc[2] = {0.0, 0.0};
     T rsum[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) rsum[a] = T(0);
     int buf = 0;
     for (int k = k0; k < k1; ++k) {
-        mgf_point_upd<T, KIND>(nxt, N, wi, wj, zw(k + 1), code, invd, r, q, alpha, omega);
+        mgf_point_upd<T, KIND>(nxt, N, wi, wj, zw(k + 1), code, invd, r, q, alpha, omega, ft);
         if (h < H) {
             MgfPt<T, KIND> hp;
-            mgf_point_upd<T, KIND>(hp, N, hi, hj, k, code, invd, r, q, alpha, omega);
+            mgf_point_upd<T, KIND>(hp, N, hi, hj, k, code, invd, r, q, alpha, omega, ft);
 #pragma unroll
             for (int a = 0; a < NB; ++a) tile[buf][a][hslot] = hp.x[a];
         }
@@ -489,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
         for (int a = 0; a < NB; ++a) {
             const T* tl = tile[buf][a];
             const T v[7] = {cur.x[a], tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev[a], nxt.x[a]};
-            rsum[a] += cur.b[a] - mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a);
+            rsum[a] += cur.b[a] - mgf_apply<T, KIND>(v, cur.cd, cxp, cyp, nxt.cd, a, ft);
         }
         if (k & 1) {
             const int cN = N >> 1;
