@@ -173,6 +173,11 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "kernel_timing" n > 0: every n-th iteration of each inner solve is launched
  *                 eagerly with each of its kernels bracketed by HIP events
  *                 (0 = off, the default); see stokes_kernel_timing
+ *   "fuse_dir_A", "fuse_dir_S"  1: in the multigrid-preconditioned solves,
+ *                 form the new direction inside the stencil kernel (one sweep;
+ *                 the direction is double-buffered); 0: a separate pointwise
+ *                 direction kernel, then the stencil.  Same results bitwise.
+ *                 Defaults: 0 for A, 1 for the SIMPLE matrix.
  *   "progress"    n > 0: one line on stderr every n outer iterations
  *                 (iteration, relative residual, permeability, elapsed
  *                 seconds); 0 = silent (default)
@@ -249,8 +254,9 @@ stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
  * 2 = A update, 3 = SIMPLE direction, 4 = SIMPLE stencil, 5 = SIMPLE update,
  * and the voxel-level multigrid kernels: 6 = A restriction, 7 = A smoothing,
  * 8 = SIMPLE restriction, 9 = SIMPLE smoothing, 10 = A update fused with the
- * restriction, 11 = SIMPLE update fused with the restriction (the update of
- * the multigrid-preconditioned solves).  Returns the total
+ * restriction, 11 = SIMPLE update fused with the restriction, 12 = A
+ * direction fused with the stencil, 13 = SIMPLE direction fused with the
+ * stencil (10..13: the multigrid-preconditioned solves).  Returns the total
  * milliseconds and the number of timed launches (launches queued after
  * convergence return at once and are counted too), and the algorithmic bytes one launch
  * moves (each input read once, each output written once, in FP64). */

@@ -902,6 +902,126 @@ __global__ void __launch_bounds__(kBlock) k_cgA_stencil_tiled(Sweep s, const uin
     write_partials<1>(acc, part, kDQ, t.lb);
 }
 
+// Direction update fused with the stencil, for the multigrid-preconditioned
+// solves: beta and the convergence test from the previous partials (as the
+// direction kernel), then dout = z + beta din (din ignored when j = 0) formed at
+// every tile and ring point, written at the own voxel, and q = M dout with the
+// partial (dout, q).  din and dout are different buffers: blocks read din at
+// their ring points while neighbouring blocks write their own points.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_tiled(Sweep s, const uint8_t* __restrict__ code,
+                                                                 const T* __restrict__ z, const T* __restrict__ din,
+                                                                 T* __restrict__ dout, T* __restrict__ q, CgState* st,
+                                                                 double* part) {
+    if (st->done) return;
+    double beta_d;
+    int j;
+    if (cg_dir_scalars(st, part, s.nblk, &beta_d, &j)) return;
+    const T beta = (T)beta_d;
+    const bool first = j == 0;
+    __shared__ T tl[2][kTileMax];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    const Tile t = tile_of(s);
+    const int N = t.N, N2 = N * N, W = t.W;
+    const int col = t.wi + N * t.wj;
+    const int hcol = t.hi + N * t.hj;
+    const int xp = t.wi == N - 1 ? col - (N - 1) : col + 1;
+    const int yp = t.wj == N - 1 ? col - (N - 1) * N : col + N;
+    auto dn = [&](int X) -> T { return first ? z[X] : z[X] + beta * din[X]; };
+    T dprev = dn(col + tile_zw(t.k0 - 1, N) * N2), dcur = dn(col + t.k0 * N2);
+    int ccur = code[col + t.k0 * N2];
+    double acc[1] = {0.0};
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int kn = tile_zw(k + 1, N);
+        const T dnext = dn(col + kn * N2);
+        const int cnext = code[col + kn * N2];
+        const int cxp = code[xp + k * N2], cyp = code[yp + k * N2];
+        if (t.ring) tl[buf][t.hslot] = dn(hcol + k * N2);
+        tl[buf][t.own] = dcur;
+        __syncthreads();
+        const T* w = tl[buf];
+        const T qv = ((ft.inv[0][ccur] * (dcur - w[t.own - 1]) + ft.inv[0][cxp] * (dcur - w[t.own + 1])) +
+                      (ft.inv[1][ccur] * (dcur - w[t.own - W]) + ft.inv[1][cyp] * (dcur - w[t.own + W]))) +
+                     (ft.inv[2][ccur] * (dcur - dprev) + ft.inv[2][cnext] * (dcur - dnext));
+        if (t.valid) {
+            dout[col + k * N2] = dcur;
+            q[col + k * N2] = qv;
+            acc[0] += (double)dcur * (double)qv;
+        }
+        dprev = dcur;
+        dcur = dnext;
+        ccur = cnext;
+        buf ^= 1;
+    }
+    write_partials<1>(acc, part, kDQ, t.lb);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const uint8_t* __restrict__ code,
+                                                                 const T* __restrict__ z, const T* __restrict__ din,
+                                                                 T* __restrict__ dout, T* __restrict__ q, CgState* st,
+                                                                 double* part) {
+    if (st->done) return;
+    double beta_d;
+    int j;
+    if (cg_dir_scalars(st, part, s.nblk, &beta_d, &j)) return;
+    const T beta = (T)beta_d;
+    const bool first = j == 0;
+    __shared__ T tl[2][3][kTileMax];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    const Tile t = tile_of(s);
+    const int N = t.N, N2 = N * N, W = t.W;
+    const size_t n3 = (size_t)s.n3;
+    const int col = t.wi + N * t.wj;
+    const int hcol = t.hi + N * t.hj;
+    auto dn = [&](size_t F) -> T { return first ? z[F] : z[F] + beta * din[F]; };
+    T dprev[3], dcur[3];
+    {
+        const int Xp = col + tile_zw(t.k0 - 1, N) * N2, Xc = col + t.k0 * N2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dprev[a] = dn(a * n3 + Xp);
+            dcur[a] = dn(a * n3 + Xc);
+        }
+    }
+    double acc[1] = {0.0};
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int Xn = col + tile_zw(k + 1, N) * N2, X = col + k * N2;
+        T dnext[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dnext[a] = dn(a * n3 + Xn);
+        const int cd = code[X];
+        if (t.ring) {
+            const int Xh = hcol + k * N2;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) tl[buf][a][t.hslot] = dn(a * n3 + Xh);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) tl[buf][a][t.own] = dcur[a];
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T* w = tl[buf][a];
+            const T nbs = ((w[t.own - 1] + w[t.own + 1]) + (w[t.own - W] + w[t.own + W])) + (dprev[a] + dnext[a]);
+            const T dg = ft.dg[a][cd];
+            const T qv = dg > T(0) ? dg * dcur[a] - nbs : T(0);
+            if (t.valid) {
+                dout[a * n3 + X] = dcur[a];
+                q[a * n3 + X] = qv;
+                acc[0] += (double)dcur[a] * (double)qv;
+            }
+            dprev[a] = dcur[a];
+            dcur[a] = dnext[a];
+        }
+        buf ^= 1;
+    }
+    write_partials<1>(acc, part, kDQ, t.lb);
+}
+
 // q = Shat d on the cells and the partial (d, q)
 template <class T>
 __global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,

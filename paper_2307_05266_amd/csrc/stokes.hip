@@ -48,7 +48,8 @@ constexpr int kCompBlocks = 256;
 // kinds of timed kernels and their algorithmic bytes per voxel (FP64)
 enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeSStencil = 4, kTimeSUpdate = 5,
        kTimeMgARestrict = 6, kTimeMgASmooth = 7, kTimeMgSRestrict = 8, kTimeMgSSmooth = 9,
-       kTimeAUpdRestrict = 10, kTimeSUpdRestrict = 11, kTimeKinds = 12 };
+       kTimeAUpdRestrict = 10, kTimeSUpdRestrict = 11, kTimeADirStencil = 12, kTimeSDirStencil = 13,
+       kTimeKinds = 14 };
 // A dir     : r, d read (3 planes each), code byte read; d written
 // A stencil : d read, code byte read; q written
 // A update  : x, d, r, q read, code byte read; x, r written
@@ -62,9 +63,12 @@ enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeS
 // S smoothing     : b, inverse diagonal, code byte, level-1 x read; y written
 // A update + restriction: x, r, d, q read (3 planes), code byte; x, r written, level-1 b written
 // S update + restriction: inverse diagonal, x, r, d, q read, code byte; x, r written, level-1 b written
+// A direction + stencil: z, d read (3 planes), code byte; d, q written (3 planes)
+// S direction + stencil: z, d read, code byte; d, q written
 constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,     6 * 8 + 1,         18 * 8 + 1,    4 * 8,
                                               2 * 8 + 1,     7 * 8,             3 * 8 + 1 + 3, 6 * 8 + 1 + 3,
-                                              2 * 8 + 1 + 1, 3 * 8 + 1 + 1,     18 * 8 + 1 + 3, 7 * 8 + 1 + 1};
+                                              2 * 8 + 1 + 1, 3 * 8 + 1 + 1,     18 * 8 + 1 + 3, 7 * 8 + 1 + 1,
+                                              12 * 8 + 1,    4 * 8 + 1};
 
 }  // namespace
 
@@ -113,11 +117,17 @@ struct stokes_ctx {
         float* z32 = nullptr;
         double* r2 = nullptr;          // fine level: second residual buffer of the fused update
         float* r2_32 = nullptr;
+        double* d2 = nullptr;          // fine level: second direction buffer of the fused direction + stencil
+        float* d2_32 = nullptr;
     };
     MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
     int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
     double mg_omega = 0.9, mg_scale = 1.7;
+    // multigrid solves: direction fused with the stencil (measured: a gain for
+    // the SIMPLE matrix; about even for A, whose fused sweep loads z and d at
+    // the ring points of three planes)
+    int fuse_dir_A = 0, fuse_dir_S = 1;
     int mg_coarse_sweeps = 16;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
@@ -488,6 +498,7 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     }
     ST_TRY(dev_alloc(c, &h.z, (size_t)nb * c->n3));
     ST_TRY(dev_alloc(c, &h.r2, (size_t)nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.d2, (size_t)nb * c->n3));
     const int m1 = nb * h.grid[1].n3;
     hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
                        h.grid[0], h.grid[1], kind, c->code, h.l64[1].D, h.l64[1].Wx, h.l64[1].Wy, h.l64[1].Wz);
@@ -520,6 +531,7 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
     }
     ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
     ST_TRY(dev_alloc(c, &h.r2_32, (size_t)h.nb * c->n3));
+    ST_TRY(dev_alloc(c, &h.d2_32, (size_t)h.nb * c->n3));
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -540,6 +552,8 @@ double* mg_out(MgHier& h, double) { return h.z; }
 float* mg_out(MgHier& h, float) { return h.z32; }
 double* mg_r2(MgHier& h, double) { return h.r2; }
 float* mg_r2(MgHier& h, float) { return h.r2_32; }
+double* mg_d2(MgHier& h, double) { return h.d2; }
+float* mg_d2(MgHier& h, float) { return h.d2_32; }
 
 // z0 = V-cycle applied to the fine residual b0; the last fine sweep writes the
 // partials of (b0, z0) into the RZ slot of the CG loop (grid = the CG sweeps').
@@ -640,28 +654,41 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
     // the fused update's 2x2x2 sums pair planes within a block
     if ((s.lz & 1) || (s.bxlog != 5 && s.bxlog != 6)) return STOKES_E_LIMIT;
     T* r2 = mg_r2(c->mgS, T());
+    T* d2 = mg_d2(c->mgS, T());
     T* bc = mg_view(c->mgS, 1, T()).b;
     const T omega = (T)c->mg_omega;
-    auto body = [c, s, st, v, z, r2, bc, omega](int parity) -> stokes_status {
+    const bool fuse = c->fuse_dir_S != 0;
+    auto body = [c, s, st, v, z, r2, d2, bc, omega, fuse](int parity) -> stokes_status {
         T* rin = parity ? r2 : v.r;
         T* rout = parity ? v.r : r2;
+        T* din = parity ? d2 : v.d;
+        T* dout = parity ? v.d : d2;
         bool open;
-        ST_TRY(time_begin(c, kTimeSDir, &open));
-        hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, rin, v.d, st, c->part,
-                           (const T*)z);
-        ST_TRY(time_end(c, open));
-        ST_TRY(time_begin(c, kTimeSStencil, &open));
-        hipLaunchKernelGGL(k_cgS_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                           c->part);
-        ST_TRY(time_end(c, open));
+        if (fuse) {
+            ST_TRY(time_begin(c, kTimeSDirStencil, &open));
+            hipLaunchKernelGGL(k_cgS_dirstencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                               (const T*)z, (const T*)din, dout, v.q, st, c->part);
+            ST_TRY(time_end(c, open));
+        } else {
+            // direction in place (pointwise), then the stencil
+            dout = v.d;
+            ST_TRY(time_begin(c, kTimeSDir, &open));
+            hipLaunchKernelGGL(k_cgS_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, rin, v.d, st, c->part,
+                               (const T*)z);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeSStencil, &open));
+            hipLaunchKernelGGL(k_cgS_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d,
+                               v.q, st, c->part);
+            ST_TRY(time_end(c, open));
+        }
         ST_TRY(time_begin(c, kTimeSUpdRestrict, &open));
         hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineShat>), grid_of(s), dim3(kBlock), 0, c->stream, s,
-                           c->code, v.invd, v.x, (const T*)rin, rout, (const T*)v.d, (const T*)v.q, bc, omega, st,
+                           c->code, v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega, st,
                            c->part);
         ST_TRY(time_end(c, open));
         return vcycle<T>(c, c->mgS, rout, v.invd, z, st, true);
     };
-    return run_inner(c, 1, graph_key<T>(2, v.x, v.r, v.d, v.q, v.invd, z), body, iters, status);
+    return run_inner(c, 1, graph_key<T>(fuse ? 2 : 4, v.x, v.r, v.d, v.q, v.invd, z), body, iters, status);
 }
 
 // Multigrid-preconditioned CG with A (three planes); stopping test on the
@@ -678,28 +705,41 @@ stokes_status cg_A_mg(stokes_ctx* c, InnerA<T> v, const double* b, double eps, i
     // the fused update's 2x2x2 sums pair planes within a block
     if ((s.lz & 1) || (s.bxlog != 5 && s.bxlog != 6)) return STOKES_E_LIMIT;
     T* r2 = mg_r2(c->mgA, T());
+    T* d2 = mg_d2(c->mgA, T());
     T* bc = mg_view(c->mgA, 1, T()).b;
     const T omega = (T)c->mg_omega;
-    auto body = [c, s, st, v, z, r2, bc, omega](int parity) -> stokes_status {
+    const bool fuse = c->fuse_dir_A != 0;
+    auto body = [c, s, st, v, z, r2, d2, bc, omega, fuse](int parity) -> stokes_status {
         T* rin = parity ? r2 : v.r;
         T* rout = parity ? v.r : r2;
+        T* din = parity ? d2 : v.d;
+        T* dout = parity ? v.d : d2;
         bool open;
-        ST_TRY(time_begin(c, kTimeADir, &open));
-        hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, rin, v.d, st, c->part,
-                           (const T*)z);
-        ST_TRY(time_end(c, open));
-        ST_TRY(time_begin(c, kTimeAStencil, &open));
-        hipLaunchKernelGGL(k_cgA_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d, v.q, st,
-                           c->part);
-        ST_TRY(time_end(c, open));
+        if (fuse) {
+            ST_TRY(time_begin(c, kTimeADirStencil, &open));
+            hipLaunchKernelGGL(k_cgA_dirstencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                               (const T*)z, (const T*)din, dout, v.q, st, c->part);
+            ST_TRY(time_end(c, open));
+        } else {
+            // direction in place (pointwise), then the stencil
+            dout = v.d;
+            ST_TRY(time_begin(c, kTimeADir, &open));
+            hipLaunchKernelGGL(k_cgA_dir<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, rin, v.d, st, c->part,
+                               (const T*)z);
+            ST_TRY(time_end(c, open));
+            ST_TRY(time_begin(c, kTimeAStencil, &open));
+            hipLaunchKernelGGL(k_cgA_stencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, v.d,
+                               v.q, st, c->part);
+            ST_TRY(time_end(c, open));
+        }
         ST_TRY(time_begin(c, kTimeAUpdRestrict, &open));
         hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineA>), grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
-                           (const T*)nullptr, v.x, (const T*)rin, rout, (const T*)v.d, (const T*)v.q, bc, omega, st,
+                           (const T*)nullptr, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega, st,
                            c->part);
         ST_TRY(time_end(c, open));
         return vcycle<T>(c, c->mgA, rout, (const T*)nullptr, z, st, true);
     };
-    return run_inner(c, 0, graph_key<T>(3, v.x, v.r, v.d, v.q, nullptr, z), body, iters, status);
+    return run_inner(c, 0, graph_key<T>(fuse ? 3 : 5, v.x, v.r, v.d, v.q, nullptr, z), body, iters, status);
 }
 
 // precision-generic dispatch between the multigrid and Jacobi inner solves
@@ -1017,7 +1057,7 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
         for (int prec = 0; prec <= precision; ++prec) {
             const int64_t w = prec == 0 ? 8 : 4;
             for (size_t l = 1; l < ns.size(); ++l) t += 7 * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
-            t += 2 * blk(nb * n3, w);   // cycle output and second residual on level 0
+            t += 3 * blk(nb * n3, w);   // cycle output, second residual and direction on level 0
         }
     }
     if (precision == 1) t += 4 * blk(3 * n3, 4) + 5 * blk(n3, 4);
@@ -1087,6 +1127,8 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         c->sw = sw;
     }
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
+    else if (k == "fuse_dir_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_A = (int)v; }
+    else if (k == "fuse_dir_S") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_S = (int)v; }
     else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }
     else return STOKES_E_ARG;
     return STOKES_OK;

@@ -379,12 +379,13 @@ def test_kernel_timing_counts_every_kind(P):
     kernels.  Bytes per launch follow the per-voxel byte model."""
     from paper_2307_05266_amd.stokes import KERNEL_NAMES
     N = 32
-    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26, 148, 58]
+    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26, 148, 58, 97, 33]
     assert len(KERNEL_NAMES) == len(per_voxel)
     with P.Stokes(spheres(N, 3.0, 0.5, 1)) as s:
-        for mg, launched in [(1, {0, 1, 3, 4, 7, 9, 10, 11}), (0, {0, 1, 2, 3, 4, 5})]:
+        for mg, launched in [(1, {7, 9, 10, 11, 12, 13}), (0, {0, 1, 2, 3, 4, 5})]:
             s.set_option("mg", mg)
             s.set_option("mg_A", mg)
+            s.set_option("fuse_dir_A", 1)
             s.set_option("kernel_timing", 1)
             s.solve(P.STOKES_SIMPLE, 1e-8)
             for kind, name in enumerate(KERNEL_NAMES):
@@ -419,4 +420,22 @@ def test_graph_replay_matches_eager_launches(P, precision):
         s.set_option("kernel_timing", 3)
         r = s.solve(P.STOKES_SIMPLE, 1e-8)
         assert r["k_hat"] == ref["k_hat"]
-        assert s.kernel_timing(0)[1] > 0
+        assert s.kernel_timing(12)[1] > 0        # the A direction + stencil kernel was timed
+
+
+def test_fused_direction_matches_separate_kernels(P):
+    """Forming the direction inside the stencil kernel (double-buffered
+    direction) or in a separate pointwise kernel gives bitwise the same solve."""
+    m = spheres(40, 3.0, 0.45, 12)
+    out = {}
+    with P.Stokes(m) as s:
+        for fa, fs in [(1, 1), (0, 0), (1, 0), (0, 1)]:
+            s.set_option("fuse_dir_A", fa)
+            s.set_option("fuse_dir_S", fs)
+            r = s.solve(P.STOKES_SIMPLE, 1e-8)
+            p, u = s.fields()
+            out[(fa, fs)] = (r["k_hat"], r["inner_A_iters"], r["inner_S_iters"], p, u)
+    ref = out[(1, 1)]
+    for key, val in out.items():
+        assert val[:3] == ref[:3], key
+        assert np.array_equal(val[3], ref[3]) and np.array_equal(val[4], ref[4]), key
