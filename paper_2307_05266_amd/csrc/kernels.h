@@ -591,51 +591,6 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __
     }
 }
 
-// q = A d on the faces and the partial (d, q)
-template <class T>
-__global__ void k_cgA_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,
-                              CgState* st, double* part) {
-    if (st->done) return;
-    const Column c = sweep_column(s);
-    double acc[1] = {0.0};
-    if (c.valid) {
-        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatchA) {
-            T v[kZBatchA][3][7];
-            int cd[kZBatchA];
-            Nbr nb[kZBatchA];
-#pragma unroll
-            for (int u = 0; u < kZBatchA; ++u) {
-                // planes past the run re-read the first plane; their results are dropped
-                nb[u] = neighbours(s, c, k0 + u < c.k1 ? k0 + u : c.k0);
-                cd[u] = code[nb[u].X];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T* __restrict__ da = d + (size_t)a * s.n3;
-                    const int idx[7] = {nb[u].X, nb[u].xm, nb[u].xp, nb[u].ym, nb[u].yp, nb[u].zm, nb[u].zp};
-#pragma unroll
-                    for (int t = 0; t < 7; ++t) v[u][a][t] = da[idx[t]];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kZBatchA; ++u) {
-                const bool in = k0 + u < c.k1;
-                const int sc[3] = {sx_of(cd[u]), sy_of(cd[u]), sz_of(cd[u])};
-                T qv[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T* w = v[u][a];
-                    const T nbs = ((w[1] + w[2]) + (w[3] + w[4])) + (w[5] + w[6]);
-                    qv[a] = sc[a] ? (T)(5 + sc[a]) * w[0] - nbs : T(0);
-                    acc[0] += in ? (double)w[0] * (double)qv[a] : 0.0;
-                }
-                if (in)
-                    for (int a = 0; a < 3; ++a) q[(size_t)a * s.n3 + nb[u].X] = qv[a];
-            }
-        }
-    }
-    write_partials<1>(acc, part, kDQ, c.lb);
-}
-
 template <class T>
 __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __restrict__ x, T* __restrict__ r,
                              const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
@@ -1020,49 +975,6 @@ __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const 
         buf ^= 1;
     }
     write_partials<1>(acc, part, kDQ, t.lb);
-}
-
-// q = Shat d on the cells and the partial (d, q)
-template <class T>
-__global__ void k_cgS_stencil(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ d, T* __restrict__ q,
-                              CgState* st, double* part) {
-    if (st->done) return;
-    const Column c = sweep_column(s);
-    double acc[1] = {0.0};
-    if (c.valid) {
-        for (int k0 = c.k0; k0 < c.k1; k0 += kZBatch) {
-            T v[kZBatch][7];
-            int cX[kZBatch], cxp[kZBatch], cyp[kZBatch], czp[kZBatch];
-            Nbr nb[kZBatch];
-#pragma unroll
-            for (int u = 0; u < kZBatch; ++u) {
-                nb[u] = neighbours(s, c, k0 + u < c.k1 ? k0 + u : c.k0);
-                const Nbr& n = nb[u];
-                const int idx[7] = {n.X, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
-#pragma unroll
-                for (int t = 0; t < 7; ++t) v[u][t] = d[idx[t]];
-                cX[u] = code[n.X];
-                cxp[u] = code[n.xp];
-                cyp[u] = code[n.yp];
-                czp[u] = code[n.zp];
-            }
-#pragma unroll
-            for (int u = 0; u < kZBatch; ++u) {
-                const bool in = k0 + u < c.k1;
-                const T* w = v[u];
-                const T dX = w[0];
-                const T qv = ((inv_diag_A_t<T>(sx_of(cX[u])) * (dX - w[1]) +
-                               inv_diag_A_t<T>(sx_of(cxp[u])) * (dX - w[2])) +
-                              (inv_diag_A_t<T>(sy_of(cX[u])) * (dX - w[3]) +
-                               inv_diag_A_t<T>(sy_of(cyp[u])) * (dX - w[4]))) +
-                             (inv_diag_A_t<T>(sz_of(cX[u])) * (dX - w[5]) +
-                              inv_diag_A_t<T>(sz_of(czp[u])) * (dX - w[6]));
-                acc[0] += in ? (double)dX * (double)qv : 0.0;
-                if (in) q[nb[u].X] = qv;
-            }
-        }
-    }
-    write_partials<1>(acc, part, kDQ, c.lb);
 }
 
 template <class T>

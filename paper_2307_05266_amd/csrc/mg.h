@@ -204,7 +204,6 @@ __device__ __forceinline__ void mg_prolong7(const MgParents& q, const T (&xp)[4]
 // Lanes past the box edge compute the value at their wrapped position, which
 // is exactly the periodic neighbour of the last voxel inside.
 // ---------------------------------------------------------------------------
-constexpr int kMgTile = 396;   // (BX + 2) (BY + 2) for BX x BY = 64 x 4 (32 x 8 needs 340)
 
 // Sum of v over the 2 x 2 in-plane blocks of voxels: the i pair by shuffle
 // (lane i^1); the j pair by shuffle (lane^32) when columns are 32 wide, else
@@ -282,31 +281,16 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
                                                       double* part, int slot, const CgState* st) {
     if (st && st->done) return;
     constexpr int NB = MgfPt<T, KIND>::NB;
-    __shared__ T tile[2][NB][kMgTile];
+    __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
     __shared__ FaceTab<T> ft;
     face_tab_fill<T>(ft);
     __syncthreads();
-    const int N = s.N;
-    const int lb = xcd_remap((int)blockIdx.x, s.nblk);
-    const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
-    const int bx = lb % s.gx, t = lb / s.gx, by = t % s.gy, bz = t / s.gy;
-    const int tx = (int)threadIdx.x & (BX - 1), ty = (int)threadIdx.x >> s.bxlog;
-    const int gi = bx * BX + tx, gj = by * BY + ty;
-    const bool valid = gi < N && gj < N;
-    const int wi = gi % N, wj = gj % N;
-    const int k0 = bz * s.lz, k1 = min(N, k0 + s.lz);
-    // ring point of this thread (if any): left, right, bottom, top edges
-    const int H = 2 * (BX + BY);
-    const int h = (int)threadIdx.x;
-    int hx = 0, hy = 0;
-    if (h < BY) { hx = -1; hy = h; }
-    else if (h < 2 * BY) { hx = BX; hy = h - BY; }
-    else if (h < 2 * BY + BX) { hx = h - 2 * BY; hy = -1; }
-    else { hx = h - 2 * BY - BX; hy = BY; }
-    const int hi = ((bx * BX + hx) % N + N) % N, hj = ((by * BY + hy) % N + N) % N;
-    const int hslot = (hy + 1) * W + (hx + 1);
-    const int own = (ty + 1) * W + (tx + 1);
+    const Tile tt = tile_of(s);
+    const int N = tt.N, W = tt.W, lb = tt.lb;
+    const int gi = tt.gi, gj = tt.gj, wi = tt.wi, wj = tt.wj, k0 = tt.k0, k1 = tt.k1;
+    const bool valid = tt.valid;
+    const int hi = tt.hi, hj = tt.hj, hslot = tt.hslot, own = tt.own;
     auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
 
     MgfPt<T, KIND> cur, nxt;
@@ -325,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
     int buf = 0;
     for (int k = k0; k < k1; ++k) {
         mgf_point<T, KIND, POST>(nxt, N, cn, wi, wj, zw(k + 1), code, invd, b, xc, scale, omega, ft);
-        if (h < H) {
+        if (tt.ring) {
             MgfPt<T, KIND> hp;
             mgf_point<T, KIND, POST>(hp, N, cn, hi, hj, k, code, invd, b, xc, scale, omega, ft);
 #pragma unroll
@@ -423,31 +407,17 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
     const T alpha = (T)alpha_d;
     constexpr int NB = MgfPt<T, KIND>::NB;
-    __shared__ T tile[2][NB][kMgTile];
+    __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[NB * kBlock / 2];
     __shared__ FaceTab<T> ft;
     face_tab_fill<T>(ft);
     __syncthreads();
-    const int N = s.N;
     const size_t n3 = (size_t)s.n3;
-    const int lb = xcd_remap((int)blockIdx.x, s.nblk);
-    const int BX = 1 << s.bxlog, BY = kBlock >> s.bxlog, W = BX + 2;
-    const int bx = lb % s.gx, t = lb / s.gx, by = t % s.gy, bz = t / s.gy;
-    const int tx = (int)threadIdx.x & (BX - 1), ty = (int)threadIdx.x >> s.bxlog;
-    const int gi = bx * BX + tx, gj = by * BY + ty;
-    const bool valid = gi < N && gj < N;
-    const int wi = gi % N, wj = gj % N;
-    const int k0 = bz * s.lz, k1 = min(N, k0 + s.lz);
-    const int H = 2 * (BX + BY);
-    const int h = (int)threadIdx.x;
-    int hx = 0, hy = 0;
-    if (h < BY) { hx = -1; hy = h; }
-    else if (h < 2 * BY) { hx = BX; hy = h - BY; }
-    else if (h < 2 * BY + BX) { hx = h - 2 * BY; hy = -1; }
-    else { hx = h - 2 * BY - BX; hy = BY; }
-    const int hi = ((bx * BX + hx) % N + N) % N, hj = ((by * BY + hy) % N + N) % N;
-    const int hslot = (hy + 1) * W + (hx + 1);
-    const int own = (ty + 1) * W + (tx + 1);
+    const Tile tt = tile_of(s);
+    const int N = tt.N, W = tt.W, lb = tt.lb;
+    const int gi = tt.gi, gj = tt.gj, wi = tt.wi, wj = tt.wj, k0 = tt.k0, k1 = tt.k1;
+    const bool valid = tt.valid;
+    const int hi = tt.hi, hj = tt.hj, hslot = tt.hslot, own = tt.own;
     auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
 
     MgfPt<T, KIND> cur, nxt;
@@ -466,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
     int buf = 0;
     for (int k = k0; k < k1; ++k) {
         mgf_point_upd<T, KIND>(nxt, N, wi, wj, zw(k + 1), code, invd, r, q, alpha, omega, ft);
-        if (h < H) {
+        if (tt.ring) {
             MgfPt<T, KIND> hp;
             mgf_point_upd<T, KIND>(hp, N, hi, hj, k, code, invd, r, q, alpha, omega, ft);
 #pragma unroll
@@ -657,7 +627,7 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       const CgState* st) {
     if (st && st->done) return;
-    __shared__ T tile[2][NB][kMgTile];
+    __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
     const Tile t = tile_of(s);
     const int n = t.N, W = t.W;
