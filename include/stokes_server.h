@@ -15,7 +15,8 @@
  * is bitwise the same alone or among others: it runs the same kernels with the
  * same deterministic reductions on its own context.
  *
- * Thread safety: every call may be made from any thread.
+ * Thread safety: every call may be made from any thread, except that no call
+ * may overlap or follow stokes_server_destroy on the same server.
  */
 #ifndef STOKES_SERVER_H
 #define STOKES_SERVER_H

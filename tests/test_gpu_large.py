@@ -80,6 +80,24 @@ def test_tight_spheres_256_mixed_and_fp64(P):
     assert abs(rm["outer_iters"] - r64["outer_iters"]) <= 10
 
 
+def test_spheres_224_partial_coarse_tiles(P):
+    """224^3: the first coarse level (112^3) runs the tiled coarse kernels on
+    64-wide columns whose second tile runs past the level's edge."""
+    m = spheres(224, 4.0, 0.4, 3)
+    say("[large] spheres 224^3 r=4 porosity 0.4 seed 3")
+    light = oracle.Oracle(m, assemble=False)
+    with P.Stokes(m, precision=1) as s:
+        assert s.info()["mg_levels_S"] == 5
+        r = s.solve(P.STOKES_SIMPLE, TOL)
+        say(f"    mixed k={r['k_hat']:.14e} outer={r['outer_iters']} t={r['seconds']:.1f}s")
+        assert r["status"] == 0
+        check_solution(s, r, light, np.random.default_rng(7))
+        s.set_option("precision", 0)
+        r64 = s.solve(P.STOKES_SIMPLE, TOL)
+        assert r64["status"] == 0
+    assert abs(r["k_hat"] - r64["k_hat"]) <= 1e-4 * r64["k_hat"]
+
+
 @pytest.mark.long
 def test_grf_512_mixed(P):
     m = grf(512, 8.0, 0.15, 0)
