@@ -93,12 +93,21 @@ def cpu_baseline(mask, gpu_rep, budget_s=20.0):
     itS = abs(itS) if itS >= 0 else -itS - 1
     tS = (time.perf_counter() - t0) / max(itS, 1)
     est = gpu_rep["inner_A_iters"] * tA + gpu_rep["inner_S_iters"] * tS
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 1.0 / est, "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
         "sample": (f"oracle on the same {N}^3 geometry: one inner A solve ({itA} iterations, "
                    f"{tA * 1e3:.1f} ms each) and {itS} inner SIMPLE iterations ({tS * 1e3:.1f} ms each), "
                    f"scaled to the {gpu_rep['inner_A_iters']} + {gpu_rep['inner_S_iters']} inner iterations "
-                   f"of one solve (outer-loop vector work not counted)"),
+                   f"of one solve (outer-loop vector work not counted); host {model or 'unknown CPU'}, "
+                   f"{os.cpu_count()} logical CPUs"),
         "seconds_per_solve_est": est,
     }
 
@@ -314,6 +323,9 @@ def main():
         "inner_S_iters": sweeps_S,
         "setup_ms": setup_ms,
         "cell_updates_per_s": (sweeps_A + sweeps_S) * N ** 3 * args.steps / total,
+        # the same over active unknowns only (faces for A, fluid cells for SIMPLE)
+        "active_dof_updates_per_s": (sweeps_A * (info["nface_x"] + info["nface_y"] + info["nface_z"]) +
+                                     sweeps_S * info["nfluid"]) * args.steps / total,
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
