@@ -55,7 +55,10 @@ def measured_traffic(kernel, N):
     (a hash of the kernel sources)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "traffic_128_spheres_inner_cg.md")
+    tables = {128: "traffic_128_spheres_inner_cg.md", 256: "traffic_256_tight_spheres.md"}
+    if N not in tables:
+        return None
+    path = os.path.join(ROOT, "profiles", tables[N])
     srcs = [os.path.join(ROOT, "paper_2307_05266_amd", "csrc", f) for f in ("kernels.h", "mg.h")]
     try:
         m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
