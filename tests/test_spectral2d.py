@@ -1,0 +1,57 @@
+"""The 2D spectral study (Sec. 4.2): the 2D operators pinned by closed forms,
+then the paper's empirical count of non-unit eigenvalues of S (eq.
+spectrum_relation), N_ev = V_surf + 3 N^2 - 1, on random square arrays.  The
+count depends on which rows of A touch a wall, not on the wall term's value
+(the slit closed form pins that).  CPU only (dense FP64)."""
+
+import numpy as np
+import pytest
+
+from oracle.spectral2d import (count_non_unit, schur_spectra, slit_flux_2d, squares_2d, surface_pixels)
+
+
+@pytest.mark.parametrize("widths", [[4], [3, 6], [5, 2, 7]])
+def test_slit_flux_closed_form_2d(widths):
+    """Plane Poiseuille flow in the 2D lattice: W (W^2 + 2) / 12 per channel of
+    W fluid rows (the same discrete closed form as in 3D)."""
+    n = 30
+    flux, m = slit_flux_2d(n, widths)
+    rows = m[:, 0]
+    ws, run = [], 0
+    for v in list(rows) + [0]:
+        if v:
+            run += 1
+        elif run:
+            ws.append(run)
+            run = 0
+    assert flux == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / n, rel=1e-12)
+
+
+def test_wall_free_box_has_unit_spectrum():
+    m = np.ones((8, 8), dtype=np.uint8)
+    ev, _ = schur_spectra(m)
+    assert count_non_unit(ev) == 1 and abs(ev.min()) < 1e-12
+
+
+def test_generator_keeps_squares_inside_their_cells():
+    for seed in range(5):
+        m = squares_2d(3, 12, 6, 2, seed)
+        assert m.shape == (36, 36)
+        # each cell holds one solid square of side n_c - n_avg, clear of the cell boundary
+        for cj in range(3):
+            for ci in range(3):
+                cell = m[cj * 12:(cj + 1) * 12, ci * 12:(ci + 1) * 12]
+                assert int((cell == 0).sum()) == 36
+                assert cell[0, :].all() and cell[-1, :].all() and cell[:, 0].all() and cell[:, -1].all()
+
+
+@pytest.mark.parametrize("N,n_c,n_avg,seed", [(2, 10, 4, 0), (2, 12, 6, 1), (3, 10, 4, 2), (3, 12, 4, 3),
+                                              (2, 16, 8, 4)])
+def test_non_unit_eigenvalue_count(N, n_c, n_avg, seed):
+    m = squares_2d(N, n_c, n_avg, 2, seed)
+    ev, evp = schur_spectra(m)
+    assert count_non_unit(ev) == surface_pixels(m) + 3 * N * N - 1
+    # S is SPSD with spectrum in [0, 1] and one zero eigenvalue (one component)
+    assert ev.min() > -1e-10 and ev.max() < 1.0 + 1e-10
+    assert int(np.sum(np.abs(ev) < 1e-10)) == 1
+    assert evp.min() > 0
