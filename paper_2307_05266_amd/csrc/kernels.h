@@ -1230,4 +1230,32 @@ __global__ void k_comp_sub(double* __restrict__ x, const uint16_t* __restrict__ 
     }
 }
 
+// One conducting component (the common case): its mean is the box mean over the
+// fluid cells, and cells outside it hold 0, so the sum runs over every cell.
+// Per-block partials of the sum, then a kernel whose every block re-adds them
+// in block order (bit-identical mean in every block) and subtracts the mean at
+// the fluid cells: two sweeps instead of three latency-bound kernels.
+__global__ void k_sum1(Sweep s, const double* __restrict__ x, double* __restrict__ part) {
+    const Column c = sweep_column(s);
+    double acc[1] = {0.0};
+    if (c.valid)
+        for (int k = c.k0; k < c.k1; ++k) acc[0] += x[c.X0 + k * s.N2];
+    write_partials<1>(acc, part, 0, c.lb);
+}
+
+__global__ void k_sub_mean1(Sweep s, double* __restrict__ x, const uint32_t* __restrict__ bits, int wpr,
+                            const double* __restrict__ part, double inv_count) {
+    const int slots[1] = {0};
+    double tot[1];
+    read_totals<1>(part, slots, s.nblk, tot);
+    const double mean = tot[0] * inv_count;
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    const uint32_t bit = 1u << (c.i & 31);
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        if (bits[((int64_t)k * s.N + c.j) * wpr + (c.i >> 5)] & bit) x[X] -= mean;
+    }
+}
+
 }  // namespace stokes

@@ -93,6 +93,7 @@ struct stokes_ctx {
     uint16_t* label = nullptr;     // only with more than one component
     double* comp_count = nullptr;  // [K]
     double* comp_part = nullptr;   // [kCompBlocks][K]
+    double* proj_part = nullptr;   // [kMaxBlocks] partials of the one-component projection
     double* comp_mean = nullptr;   // [K]
     double *fx = nullptr, *fr = nullptr, *fq = nullptr, *u = nullptr;  // faces
     double* fd = nullptr;                                               // faces, inner direction
@@ -766,6 +767,13 @@ stokes_status solve_A64(stokes_ctx* c, const double* b, double eps, int* iters, 
 stokes_status project(stokes_ctx* c, double* x) {
     const int K = c->ncomp_kept;
     if (K == 0) return STOKES_OK;
+    if (K == 1 && !c->label) {
+        hipLaunchKernelGGL(k_sum1, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, (const double*)x, c->proj_part);
+        hipLaunchKernelGGL(k_sub_mean1, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, x, c->bits, c->wpr,
+                           (const double*)c->proj_part, 1.0 / (double)c->nfluid);
+        HIP_TRY(hipGetLastError());
+        return STOKES_OK;
+    }
     const int64_t chunk = ((c->n3 + kCompBlocks - 1) / kCompBlocks + 255) / 256 * 256;
     const int nb = (int)((c->n3 + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_comp_sum, dim3(nb), dim3(kBlock), (size_t)kWaves * K * sizeof(double), c->stream, x,
@@ -907,6 +915,7 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     ST_TRY(dev_alloc(c, &c->code, (size_t)n3));
     ST_TRY(dev_alloc(c, &c->comp_count, (size_t)K));
     ST_TRY(dev_alloc(c, &c->comp_part, (size_t)kCompBlocks * K));
+    ST_TRY(dev_alloc(c, &c->proj_part, (size_t)kMaxBlocks));
     ST_TRY(dev_alloc(c, &c->comp_mean, (size_t)K));
     if (g.ncomp_kept > 1) ST_TRY(dev_alloc(c, &c->label, (size_t)n3));
     for (double** f : {&c->fx, &c->fr, &c->fq, &c->u, &c->fd})
@@ -1050,7 +1059,8 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
     int64_t t = blk((int64_t)N * N * wpr, 4) + blk(n3, 1) + blk(K, 8) + blk((int64_t)kCompBlocks * K, 8) +
                 blk(K, 8) + blk(n3, 2);
     t += 5 * blk(3 * n3, 8) + 9 * blk(n3, 8);
-    t += blk(2, sizeof(CgState)) + blk((int64_t)kNumSlots * kMaxBlocks, 8) + blk(3 * (int64_t)kMaxBlocks, 8);
+    t += blk(2, sizeof(CgState)) + blk((int64_t)kNumSlots * kMaxBlocks, 8) + blk(3 * (int64_t)kMaxBlocks, 8) +
+         blk(kMaxBlocks, 8);
     for (int nb : {1, 3}) {
         const std::vector<int> ns = mg_plan(N, nb);
         if (ns.size() < 2) continue;
