@@ -69,7 +69,10 @@ typedef enum {
     STOKES_OP_DIAG_A = 4,       /* -> faces: diag(A) on active faces (input ignored) */
     STOKES_OP_DIAG_SHAT = 5,    /* -> cells: diag(B diag(A)^{-1} B^T) (input ignored) */
     STOKES_OP_PROJECT = 6,      /* cells -> cells: remove each component's mean */
-    STOKES_OP_S = 7             /* cells -> cells: B A^{-1} B^T p with an inner solve at eps_A */
+    STOKES_OP_S = 7,            /* cells -> cells: B A^{-1} B^T p with an inner solve at eps_A */
+    STOKES_OP_MG_SHAT = 8,      /* cells -> cells: one V-cycle of the SIMPLE-matrix multigrid preconditioner
+                                   (STOKES_E_LIMIT when the geometry has no hierarchy) */
+    STOKES_OP_MG_A = 9          /* faces -> faces: one V-cycle of the multigrid preconditioner of A (same) */
 } stokes_op;
 
 /* setup flags */
@@ -194,6 +197,10 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "mg_omega", "mg_scale", "mg_coarse_sweeps"  V-cycle smoothing weight
  *                 (0.9), coarse-correction scale (1.7, below 2 keeps it SPD),
  *                 coarsest-level sweeps (16)
+ *   "mg_coarse_gs" 1 (default): coarse levels with a side below 64 (and not
+ *                 the coarsest) smooth by symmetric red-black Gauss-Seidel
+ *                 (red then black going down, black then red going up);
+ *                 0: damped Jacobi with "mg_omega", like the finer levels
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

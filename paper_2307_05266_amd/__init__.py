@@ -38,4 +38,6 @@ from .stokes import (  # noqa: F401
     STOKES_OP_DIAG_SHAT,
     STOKES_OP_PROJECT,
     STOKES_OP_S,
+    STOKES_OP_MG_SHAT,
+    STOKES_OP_MG_A,
 )

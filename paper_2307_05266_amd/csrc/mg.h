@@ -197,7 +197,7 @@ __device__ __forceinline__ void mg_prolong7(const MgParents& q, const T (&xp)[4]
 // ---------------------------------------------------------------------------
 // Level 0, LDS-tiled: each block marches its BX x BY column through z.  The
 // smoothed iterate (x0 = omega D^-1 b for the restriction, x' = x0 + scale P xc
-// for the post-smoothing) is computed once per point: a thread keeps its own
+// for the post-smoothing, 0 where D = 0) is computed once per point: a thread keeps its own
 // column's values at k-1, k, k+1 in registers, and plane k of the tile plus
 // a one-voxel ring (computed by the first 2 (BX + BY) threads) goes through
 // LDS (double-buffered, one barrier per plane) for the in-plane neighbours.
@@ -266,7 +266,9 @@ __device__ __forceinline__ void mgf_point(MgfPt<T, KIND>& q, int N, int cn, int 
     for (int a = 0; a < NB; ++a) {
         if (KIND == kMgFineA) q.inv[a] = ft.inv[a][q.cd];
         q.x[a] = omega * q.inv[a] * q.b[a];
-        if (POST) q.x[a] += scale * e[a];
+        // the prolonged correction is held at 0 on nodes that are not unknowns:
+        // A's stencil sums all six neighbours, and a wall must read as zero
+        if (POST && q.inv[a] > T(0)) q.x[a] += scale * e[a];
     }
 }
 
@@ -279,7 +281,6 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
                                                       const T* __restrict__ invd, const T* __restrict__ b,
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       double* part, int slot, const CgState* st) {
-    if (st && st->done) return;
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
@@ -302,6 +303,8 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
     mgf_point<T, KIND, POST>(cur, N, cn, wi, wj, k0, code, invd, b, xc, scale, omega, ft);
+    // a finished solve is checked after the first loads (in bounds either way)
+    if (st && st->done) return;
     double acc = 0.0;       // POST: partial of (b, y)
     T rsum[NB];             // restriction: residual summed over the plane pair
 #pragma unroll
@@ -540,7 +543,6 @@ __device__ __forceinline__ T mgc_apply(const MgcPoint<T>& m, const T (&v)[7]) {
 template <class T>
 __global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict__ b, T* __restrict__ bc, T omega,
                                const CgState* st) {
-    if (st && st->done) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int I = t >> 3, ch = t & 7;
     T r = T(0);
@@ -558,6 +560,9 @@ __global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict
     r += __shfl_xor(r, 1, 64);
     r += __shfl_xor(r, 2, 64);
     r += __shfl_xor(r, 4, 64);
+    // a finished solve is checked after the loads (in bounds either way), so
+    // its latency overlaps theirs; nothing is written then
+    if (st && st->done) return;
     if (ch == 0 && I < cg.nb * cg.n3) bc[I] = r;
 }
 
@@ -566,7 +571,6 @@ __global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict
 template <class T>
 __global__ void k_mgc_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, const T* __restrict__ xc, int cn,
                                  T scale, T omega, T* __restrict__ y, const CgState* st) {
-    if (st && st->done) return;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= g.nb * g.n3) return;
     const int p = I / g.n3, X = I - p * g.n3;
@@ -581,7 +585,226 @@ __global__ void k_mgc_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, con
 #pragma unroll
     for (int t = 0; t < 7; ++t) v[t] = omega * m.inv[t] * m.b[t] + e[t];
     const T ax = mgc_apply<T>(m, v);
+    if (st && st->done) return;
     y[I] = m.inv[0] > T(0) ? v[0] + omega * m.inv[0] * (m.b[0] - ax) : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Levels >= 1 below the tiled size, red-black Gauss-Seidel smoothing.  Colour
+// of node (i, j, k): (i + j + k) & 1, red = 0 (such levels have an even side,
+// so the colouring is periodic and a 7-point row couples only opposite
+// colours).  A relaxation solves the node's row for its own value,
+// x = (b + sum of W x over the six neighbours) / D, and keeps 0 where D = 0.
+// Down: red, then black, from zero; up: black, then red (the adjoint order,
+// so the cycle stays symmetric for CG).
+// One workgroup per brick of kGsB^3 nodes of one plane.  The brick's window
+// with two halo layers sits in LDS: red values from zero depend only on b, so
+// they are formed over the whole window; black values then over the first
+// halo layer, which is all the brick's own rows read.  Nothing crosses a
+// workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kGsB = 8;                               // brick side (even: a coarse node's children stay together)
+constexpr int kGsW = kGsB + 4;                        // window side
+constexpr int kGsThreads = kGsB * kGsB * kGsB;        // one interior node per thread
+constexpr int kGsWin = kGsW * kGsW * kGsW;
+constexpr int kGsBlack1 = (kGsB + 2) * (kGsB + 2) * (kGsB + 2) / 2;   // black nodes of brick + first layer
+static_assert(kGsBlack1 <= kGsThreads, "one black node of the first layer per thread");
+
+struct GsBrick {
+    int p;          // plane
+    int o[3];       // origin (global coordinates of the brick's first node)
+};
+
+__device__ __forceinline__ GsBrick gs_brick(const MgGrid& g) {
+    const int nbk = (g.n + kGsB - 1) / kGsB;
+    int b = blockIdx.x;
+    GsBrick r;
+    r.p = b / (nbk * nbk * nbk);
+    b -= r.p * nbk * nbk * nbk;
+    r.o[0] = (b % nbk) * kGsB;
+    r.o[1] = ((b / nbk) % nbk) * kGsB;
+    r.o[2] = (b / (nbk * nbk)) * kGsB;
+    return r;
+}
+
+// Window point (wx, wy, wz) is global node o + w - 2, wrapped (the side is at
+// least 10, so one wrap suffices).
+
+// Row of one node: b, D, 1/D and the couplings to -x, +x, -y, +y, -z, +z
+template <class T>
+struct GsRow {
+    T b, d, inv, w[6];
+};
+
+template <class T>
+__device__ __forceinline__ void gs_row(GsRow<T>& r, const MgGrid& g, const MgOp& op, const T* __restrict__ b,
+                                       const GsBrick& k, int wx, int wy, int wz) {
+    const size_t o = (size_t)k.p * g.n3;
+    const int i = wrapc(k.o[0] + wx - 2, g.n), j = wrapc(k.o[1] + wy - 2, g.n), kk = wrapc(k.o[2] + wz - 2, g.n);
+    const int X = i + g.n * (j + g.n * kk);
+    const T* D = (const T*)op.D + o;
+    const T* Wx = (const T*)op.Wx + o;
+    const T* Wy = (const T*)op.Wy + o;
+    const T* Wz = (const T*)op.Wz + o;
+    r.b = b[o + X];
+    r.d = D[X];
+    r.w[0] = Wx[X];
+    r.w[1] = Wx[mg_idx(g, i + 1, j, kk)];
+    r.w[2] = Wy[X];
+    r.w[3] = Wy[mg_idx(g, i, j + 1, kk)];
+    r.w[4] = Wz[X];
+    r.w[5] = Wz[mg_idx(g, i, j, kk + 1)];
+    r.inv = r.d > T(0) ? T(1) / r.d : T(0);
+}
+
+// sum of W x over the six neighbours of window point w
+template <class T>
+__device__ __forceinline__ T gs_nbsum(const GsRow<T>& r, const T* x, int w) {
+    constexpr int sy = kGsW, sz = kGsW * kGsW;
+    return ((r.w[0] * x[w - 1] + r.w[1] * x[w + 1]) + (r.w[2] * x[w - sy] + r.w[3] * x[w + sy])) +
+           (r.w[4] * x[w - sz] + r.w[5] * x[w + sz]);
+}
+
+// Interior node of thread t: the eight children of a coarse node in eight
+// consecutive lanes (bit 0: x, 1: y, 2: z), coarse nodes of the brick 4 x 4 x 4.
+__device__ __forceinline__ void gs_interior(int t, int& lx, int& ly, int& lz) {
+    const int ch = t & 7, cb = t >> 3;
+    lx = 2 * (cb & 3) + (ch & 1);
+    ly = 2 * ((cb >> 2) & 3) + ((ch >> 1) & 1);
+    lz = 2 * (cb >> 4) + (ch >> 2);
+}
+
+// Black node q < kGsBlack1 of the brick plus its first halo layer (window
+// coordinates 1 .. kGsB + 2): five per row of ten, x chosen by row parity.
+__device__ __forceinline__ void gs_black1(int q, int& wx, int& wy, int& wz) {
+    constexpr int half = (kGsB + 2) / 2;
+    wz = 1 + q / (half * (kGsB + 2));
+    wy = 1 + (q / half) % (kGsB + 2);
+    wx = 1 + 2 * (q % half) + ((wy + wz) & 1);
+}
+
+constexpr int kGsPer = (kGsWin + kGsThreads - 1) / kGsThreads;   // window points per thread
+
+__device__ __forceinline__ bool gs_red(int w) {
+    return (((w % kGsW) + ((w / kGsW) % kGsW) + w / (kGsW * kGsW)) & 1) == 0;
+}
+
+// b and D (and, for the post-smoothing, the parent's coarse correction) at the
+// red window points w = threadIdx.x + q * kGsThreads; black points and points
+// past the window load nothing.
+template <class T, bool POST>
+__device__ __forceinline__ void gs_window_loads(const MgGrid& g, const GsBrick& k, const MgOp& op,
+                                                const T* __restrict__ b, const T* __restrict__ xc, int cn,
+                                                T (&bv)[kGsPer], T (&dv)[kGsPer], T* ev) {
+    const T* D = (const T*)op.D + (size_t)k.p * g.n3;
+    const T* bp = b + (size_t)k.p * g.n3;
+    const T* xa = POST ? xc + (size_t)k.p * cn * cn * cn : nullptr;
+#pragma unroll
+    for (int q = 0; q < kGsPer; ++q) {
+        const int w = (int)threadIdx.x + q * kGsThreads;
+        bv[q] = T(0);
+        dv[q] = T(0);
+        if (POST) ev[q] = T(0);
+        if (w < kGsWin && gs_red(w)) {
+            const int wx = w % kGsW, wy = (w / kGsW) % kGsW, wz = w / (kGsW * kGsW);
+            const int i = wrapc(k.o[0] + wx - 2, g.n), j = wrapc(k.o[1] + wy - 2, g.n),
+                      kk = wrapc(k.o[2] + wz - 2, g.n);
+            const int X = i + g.n * (j + g.n * kk);
+            bv[q] = bp[X];
+            dv[q] = D[X];
+            if (POST) ev[q] = xa[(i >> 1) + cn * ((j >> 1) + cn * (kk >> 1))];
+        }
+    }
+}
+
+// bc = P^T (b - A x), x = the red-then-black relaxation of A x = b from zero.
+template <class T>
+__global__ void __launch_bounds__(kGsThreads) k_mgc_gs_restrict(MgGrid g, MgGrid cg, MgOp op,
+                                                                const T* __restrict__ b, T* __restrict__ bc,
+                                                                const CgState* st) {
+    __shared__ T sx[kGsWin];
+    const GsBrick k = gs_brick(g);
+    const int t = threadIdx.x;
+    // every load is issued before the first store: the window's red points
+    // first (the first phase needs them), then the rows of this thread's nodes
+    T bv[kGsPer], dv[kGsPer];
+    gs_window_loads<T, false>(g, k, op, b, nullptr, 0, bv, dv, nullptr);
+    int lx, ly, lz;
+    gs_interior(t, lx, ly, lz);
+    const bool inside = k.o[0] + lx < g.n && k.o[1] + ly < g.n && k.o[2] + lz < g.n;
+    const bool has_black = t < kGsBlack1;
+    int bx = 1, by = 1, bz = 1;
+    if (has_black) gs_black1(t, bx, by, bz);
+    GsRow<T> ri, rb;
+    if (inside) gs_row(ri, g, op, b, k, lx + 2, ly + 2, lz + 2);
+    if (has_black) gs_row(rb, g, op, b, k, bx, by, bz);
+    // a finished solve is checked after the loads (in bounds either way)
+    if (st && st->done) return;
+    // red values over the window (black ones are written below where read)
+#pragma unroll
+    for (int q = 0; q < kGsPer; ++q) {
+        const int w = t + q * kGsThreads;
+        if (w < kGsWin) sx[w] = gs_red(w) ? (dv[q] > T(0) ? T(1) / dv[q] : T(0)) * bv[q] : T(0);
+    }
+    __syncthreads();
+    if (has_black) {
+        const int w = bx + kGsW * (by + kGsW * bz);
+        sx[w] = rb.inv * (rb.b + gs_nbsum(rb, sx, w));
+    }
+    __syncthreads();
+    T r = T(0);
+    if (inside) {
+        const int w = (lx + 2) + kGsW * ((ly + 2) + kGsW * (lz + 2));
+        r = ri.b - (ri.d * sx[w] - gs_nbsum(ri, sx, w));
+    }
+    r += __shfl_xor(r, 1, 64);
+    r += __shfl_xor(r, 2, 64);
+    r += __shfl_xor(r, 4, 64);
+    if ((t & 7) == 0 && inside) {
+        const int ci = (k.o[0] >> 1) + (lx >> 1), cj = (k.o[1] >> 1) + (ly >> 1), ck = (k.o[2] >> 1) + (lz >> 1);
+        bc[(size_t)k.p * cg.n3 + ci + cg.n * (cj + cg.n * ck)] = r;
+    }
+}
+
+// y = the black-then-red relaxation of A y = b starting from x' = x + scale P xc,
+// x = the red-then-black relaxation from zero (its black values are not
+// needed: a black relaxation overwrites them).
+template <class T>
+__global__ void __launch_bounds__(kGsThreads) k_mgc_gs_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b,
+                                                                  const T* __restrict__ xc, int cn, T scale,
+                                                                  T* __restrict__ y, const CgState* st) {
+    __shared__ T sx[kGsWin];
+    const GsBrick k = gs_brick(g);
+    const int t = threadIdx.x;
+    T bv[kGsPer], dv[kGsPer], ev[kGsPer];
+    gs_window_loads<T, true>(g, k, op, b, xc, cn, bv, dv, ev);
+    int lx, ly, lz;
+    gs_interior(t, lx, ly, lz);
+    const bool inside = k.o[0] + lx < g.n && k.o[1] + ly < g.n && k.o[2] + lz < g.n;
+    const bool has_black = t < kGsBlack1;
+    int bx = 1, by = 1, bz = 1;
+    if (has_black) gs_black1(t, bx, by, bz);
+    GsRow<T> ri, rb;
+    if (inside) gs_row(ri, g, op, b, k, lx + 2, ly + 2, lz + 2);
+    if (has_black) gs_row(rb, g, op, b, k, bx, by, bz);
+    if (st && st->done) return;
+#pragma unroll
+    for (int q = 0; q < kGsPer; ++q) {
+        const int w = t + q * kGsThreads;
+        if (w < kGsWin)
+            sx[w] = gs_red(w) ? (dv[q] > T(0) ? T(1) / dv[q] : T(0)) * bv[q] + scale * ev[q] : T(0);
+    }
+    __syncthreads();
+    if (has_black) {
+        const int w = bx + kGsW * (by + kGsW * bz);
+        sx[w] = rb.inv * (rb.b + gs_nbsum(rb, sx, w));
+    }
+    __syncthreads();
+    if (inside) {
+        const int w = (lx + 2) + kGsW * ((ly + 2) + kGsW * (lz + 2));
+        const T v = ((lx + ly + lz) & 1) ? sx[w] : ri.inv * (ri.b + gs_nbsum(ri, sx, w));
+        y[(size_t)k.p * g.n3 + (k.o[0] + lx) + g.n * ((k.o[1] + ly) + g.n * (k.o[2] + lz))] = v;
+    }
 }
 
 // Levels >= 1 with a side of at least 32, LDS-tiled like level 0: the
@@ -626,7 +849,6 @@ template <class T, int NB, bool POST>
 __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, const T* __restrict__ b,
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       const CgState* st) {
-    if (st && st->done) return;
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
     const Tile t = tile_of(s);
@@ -644,6 +866,8 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
     mgc_point<T, NB, POST>(cur, n, cn, t.wi, t.wj, t.k0, op, b, xc, scale, omega);
+    // a finished solve is checked after the first loads (in bounds either way)
+    if (st && st->done) return;
     T rsum[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) rsum[a] = T(0);
@@ -711,7 +935,6 @@ constexpr int kMgCoarsestPer = kMgCoarsestMax / kMgCoarsestThreads;
 template <class T>
 __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __restrict__ xout, T omega, int sweeps,
                               const CgState* st) {
-    if (st && st->done) return;
     __shared__ T xs[2][kMgCoarsestMax];
     const int n = g.nb * g.n3;
     // per node: omega/D, b, the six couplings and the six neighbour slots
@@ -744,6 +967,12 @@ __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __r
         w[q][5] = Wz[nbr[q][5]];
         wd[q] = dg[q] > T(0) ? omega / dg[q] : T(0);
         bb[q] = b[Ic];
+    }
+    // a finished solve is checked after the loads (in bounds either way)
+    if (st && st->done) return;
+#pragma unroll
+    for (int q = 0; q < kMgCoarsestPer; ++q) {
+        const int I = threadIdx.x + q * kMgCoarsestThreads;
         if (I < n) xs[0][I] = wd[q] * bb[q];
     }
     __syncthreads();

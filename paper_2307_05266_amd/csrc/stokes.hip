@@ -130,6 +130,8 @@ struct stokes_ctx {
     // the ring points of three planes)
     int fuse_dir_A = 0, fuse_dir_S = 1;
     int mg_coarse_sweeps = 16;
+    // coarse levels below the tiled size: 1 red-black Gauss-Seidel, 0 damped Jacobi
+    int mg_coarse_gs = 1;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -458,6 +460,16 @@ int flat_blocks(int n, int cap = 2048) { return std::max(1, std::min(cap, (n + k
 unsigned exact_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 using MgHier = stokes_ctx::MgHier;
 
+// red-black Gauss-Seidel kernels: one workgroup per brick of kGsB^3 nodes of a
+// plane.  A window reaches two nodes past its brick and is wrapped once, which
+// holds for sides above kGsB; levels that are restricted further have an even
+// side with more than 512 nodes, so at least 10.
+constexpr int kGsMinSide = kGsB + 2;
+unsigned gs_blocks(const MgGrid& g) {
+    const int nbk = (g.n + kGsB - 1) / kGsB;
+    return (unsigned)(g.nb * nbk * nbk * nbk);
+}
+
 // Levels: halve while the side is even and a level holds more than 512 nodes
 // per plane; the coarsest level must fit one workgroup's LDS.
 // Coarse levels with a side of at least this run the LDS-tiled kernels (over a
@@ -597,6 +609,9 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
             else
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
+        } else if (c->mg_coarse_gs && h.grid[l].n >= kGsMinSide) {
+            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
         } else {
             hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0,
                                c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
@@ -621,6 +636,9 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
             else
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
+        } else if (c->mg_coarse_gs && h.grid[l].n >= kGsMinSide) {
+            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, v.y, st);
         } else {
             hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream,
                                h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y,
@@ -1129,6 +1147,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "mg_omega") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->mg_omega = v; }
     else if (k == "mg_scale") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale = v; }
     else if (k == "mg_coarse_sweeps") { if (v < 1 || v > 1000) return STOKES_E_ARG; c->mg_coarse_sweeps = (int)v; }
+    else if (k == "mg_coarse_gs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->mg_coarse_gs = (int)v; }
     else if (k == "sweep_blocks") {
         if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
         const Sweep sw = make_sweep(c->N, (int)v);
@@ -1551,8 +1570,8 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
                                 hipMemcpyKind kout) {
     const Sweep& s = c->sw;
     const int64_t n3 = c->n3;
-    const bool face_in = op == STOKES_OP_A || op == STOKES_OP_B;
-    const bool face_out = op == STOKES_OP_A || op == STOKES_OP_BT || op == STOKES_OP_DIAG_A;
+    const bool face_in = op == STOKES_OP_A || op == STOKES_OP_B || op == STOKES_OP_MG_A;
+    const bool face_out = op == STOKES_OP_A || op == STOKES_OP_BT || op == STOKES_OP_DIAG_A || op == STOKES_OP_MG_A;
     const bool no_in = op == STOKES_OP_DIAG_A || op == STOKES_OP_DIAG_SHAT;
     double* src = face_in ? c->fd : c->sd;
     double* dst = face_out ? c->fq : c->sq;
@@ -1581,6 +1600,14 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
         hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx, dst);
         break;
     }
+    case STOKES_OP_MG_SHAT:
+        if (c->mgS.levels < 1) return STOKES_E_LIMIT;
+        ST_TRY(vcycle<double>(c, c->mgS, src, c->invdS, dst, nullptr));
+        break;
+    case STOKES_OP_MG_A:
+        if (c->mgA.levels < 1) return STOKES_E_LIMIT;
+        ST_TRY(vcycle<double>(c, c->mgA, src, (const double*)nullptr, dst, nullptr));
+        break;
     default: return STOKES_E_ARG;
     }
     HIP_TRY(hipGetLastError());
@@ -1589,14 +1616,14 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
 }
 
 stokes_status stokes_apply(stokes_ctx* c, int op, const double* in, double* out) {
-    if (!c || !out || op < 0 || op > STOKES_OP_S) return STOKES_E_ARG;
+    if (!c || !out || op < 0 || op > STOKES_OP_MG_A) return STOKES_E_ARG;
     ST_TRY(apply_impl(c, op, in, out, hipMemcpyHostToDevice, hipMemcpyDeviceToHost));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return STOKES_OK;
 }
 
 stokes_status stokes_apply_device(stokes_ctx* c, int op, const double* in, double* out) {
-    if (!c || !out || op < 0 || op > STOKES_OP_S) return STOKES_E_ARG;
+    if (!c || !out || op < 0 || op > STOKES_OP_MG_A) return STOKES_E_ARG;
     return apply_impl(c, op, in, out, hipMemcpyDeviceToDevice, hipMemcpyDeviceToDevice);
 }
 

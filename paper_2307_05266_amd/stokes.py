@@ -23,7 +23,7 @@ STOKES_E_ARG, STOKES_E_NOMEM, STOKES_E_DEVICE, STOKES_E_BREAKDOWN, STOKES_E_STAT
     -1, -2, -3, -4, -5, -6
 STOKES_UZAWA, STOKES_SIMPLE = 0, 1
 (STOKES_OP_A, STOKES_OP_B, STOKES_OP_BT, STOKES_OP_SHAT, STOKES_OP_DIAG_A, STOKES_OP_DIAG_SHAT,
- STOKES_OP_PROJECT, STOKES_OP_S) = range(8)
+ STOKES_OP_PROJECT, STOKES_OP_S, STOKES_OP_MG_SHAT, STOKES_OP_MG_A) = range(10)
 STOKES_KEEP_ALL_COMPONENTS = 0x1
 STOKES_FLAG_NO_FLOW, STOKES_FLAG_ZERO_RHS, STOKES_FLAG_INNER_MAXIT = 0x1, 0x2, 0x4
 
@@ -210,8 +210,8 @@ def stokes_get_fields(ctx, N):
 
 
 def _op_shapes(op, N):
-    face_in = op in (STOKES_OP_A, STOKES_OP_B)
-    face_out = op in (STOKES_OP_A, STOKES_OP_BT, STOKES_OP_DIAG_A)
+    face_in = op in (STOKES_OP_A, STOKES_OP_B, STOKES_OP_MG_A)
+    face_out = op in (STOKES_OP_A, STOKES_OP_BT, STOKES_OP_DIAG_A, STOKES_OP_MG_A)
     return (3 * N ** 3 if face_in else N ** 3), (3 * N ** 3 if face_out else N ** 3), face_out
 
 

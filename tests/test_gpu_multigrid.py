@@ -1,0 +1,184 @@
+"""GPU tests of the multigrid preconditioner of the inner solves.
+
+One V-cycle applied through the C ABI (STOKES_OP_MG_SHAT, STOKES_OP_MG_A) is
+compared element by element with an independent scipy model of the same
+cycle, built from the oracle's assembled matrices: 2x2x2 aggregation with
+Galerkin coarse operators, damped Jacobi on level 0 and on the coarse levels
+with a side of 64 or more, red-black Gauss-Seidel (red then black going down,
+black then red going up) on the smaller coarse levels, damped-Jacobi sweeps
+from zero on the coarsest level, a scaled coarse correction.  The cycle is
+the preconditioner the library gives the role of the paper's algebraic
+multigrid (Sec. 3.2); the paper does not define it, so the model pins the
+implementation, not a formula of the paper.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from synth import spheres
+
+pytestmark = pytest.mark.gpu
+
+OMEGA, SCALE, SWEEPS, TILED_MIN_SIDE = 0.9, 1.7, 16, 64
+VC_TOL = 1e-11        # relative to the largest entry of the cycle's output
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_05266_amd as P
+    P.load()
+    return P
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mg_plan(N, nb):
+    """Level sides: halve while even, at least 2 and above 512 nodes; the
+    coarsest level (all planes) must hold at most 2048 nodes."""
+    ns, n = [N], N
+    while n % 2 == 0 and n // 2 >= 2 and n ** 3 > 512:
+        n //= 2
+        ns.append(n)
+    return ns if len(ns) > 1 and nb * n ** 3 <= 2048 else ns[:1]
+
+
+def aggregation(n):
+    X = np.arange(n ** 3)
+    i, j, k = X % n, (X // n) % n, X // (n * n)
+    h = n // 2
+    return sp.csr_matrix((np.ones(n ** 3), (X, (i // 2) + h * ((j // 2) + h * (k // 2)))), shape=(n ** 3, h ** 3))
+
+
+def black(n):
+    X = np.arange(n ** 3)
+    return ((X % n + (X // n) % n + X // (n * n)) & 1).astype(bool)
+
+
+def hierarchy(A0, ns):
+    """[(side, A, 1/D)] over the full grids of the levels, and the aggregations."""
+    levels, Ps = [], []
+    A = A0.tocsr()
+    for l, n in enumerate(ns):
+        d = A.diagonal()
+        levels.append((n, A, np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)))
+        if l + 1 < len(ns):
+            Pm = aggregation(n)
+            Ps.append(Pm)
+            A = (Pm.T @ A @ Pm).tocsr()
+    return levels, Ps
+
+
+def relax(A, inv, x, b, mask):
+    """Gauss-Seidel on the nodes of `mask` (no two of them coupled): each solves its row."""
+    off = A - sp.diags(A.diagonal())
+    y = x.copy()
+    y[mask] = (inv * (b - off @ x))[mask]
+    return y
+
+
+def cycle(levels, Ps, b, gs, l=0):
+    n, A, inv = levels[l]
+    L = len(levels) - 1
+    if l == L:
+        x = OMEGA * inv * b
+        for _ in range(SWEEPS - 1):
+            x = x + OMEGA * inv * (b - A @ x)
+        return x
+    use_gs = gs and l >= 1 and n < TILED_MIN_SIDE
+    if use_gs:
+        blk = black(n)
+        x = relax(A, inv, np.zeros_like(b), b, ~blk)
+        x = relax(A, inv, x, b, blk)
+    else:
+        x = OMEGA * inv * b
+    xc = cycle(levels, Ps, Ps[l].T @ (b - A @ x), gs, l + 1)
+    x = x + SCALE * (Ps[l] @ xc)
+    if use_gs:
+        x = relax(A, inv, x, b, blk)
+        return relax(A, inv, x, b, ~blk)
+    # nodes that are not unknowns (D = 0) are held at 0
+    return np.where(inv > 0, x + OMEGA * inv * (b - A @ x), 0.0)
+
+
+def embed(M, pos, n3):
+    """Matrix over the unknowns at grid positions `pos` -> matrix over the full grid."""
+    E = sp.csr_matrix((np.ones(len(pos)), (pos, np.arange(len(pos)))), shape=(n3, len(pos)))
+    return (E @ M @ E.T).tocsr()
+
+
+CASES = [(36, 2), (48, 5), (128, 0)]
+
+
+@pytest.mark.parametrize("N,seed", CASES)
+@pytest.mark.parametrize("gs", [1, 0])
+def test_vcycle_matches_model(P, N, seed, gs):
+    m = spheres(N, 3.0 if N < 128 else 6.0, 0.45 if N < 128 else 0.5, seed)
+    o = oracle.Oracle(m)
+    n3 = N ** 3
+    fpos, cpos = o.unknowns()
+    rng = np.random.default_rng(100 + N)
+    # SIMPLE matrix B diag(A)^-1 B^T over the cells
+    B = o.csr("B")
+    dA = o.csr("A").diagonal()
+    Shat = embed((B @ sp.diags(1.0 / dA) @ B.T).tocsr(), cpos, n3)
+    lv, Ps = hierarchy(Shat, mg_plan(N, 1))
+    b = np.zeros(n3)
+    b[cpos] = rng.standard_normal(len(cpos))
+    ba = np.zeros(3 * n3)
+    ba[fpos] = rng.standard_normal(len(fpos))
+    nsA = mg_plan(N, 3)
+    with P.Stokes(m) as s:
+        s.set_option("mg_coarse_gs", gs)
+        info = s.info()
+        z = s.apply(P.STOKES_OP_MG_SHAT, b).reshape(-1)
+        if len(nsA) > 1:
+            assert not s.apply(P.STOKES_OP_MG_A, np.zeros(3 * n3)).any()
+            za = s.apply(P.STOKES_OP_MG_A, ba).reshape(3, n3)
+        else:
+            with pytest.raises(P.StokesError):
+                s.apply(P.STOKES_OP_MG_A, ba)
+    assert info["mg_levels_S"] == len(lv) - 1
+    assert info["mg_levels_A"] == len(nsA) - 1
+    ref = cycle(lv, Ps, b, gs)
+    err = np.abs(z - ref).max() / np.abs(ref).max()
+    say(f"    N={N} gs={gs} SIMPLE V-cycle: levels {[x[0] for x in lv]} max rel err {err:.2e}")
+    assert err < VC_TOL
+    # A: block-diagonal over the three face planes, one hierarchy per plane
+    if len(nsA) < 2:
+        return
+    Af = o.csr("A")
+    plane = fpos // n3
+    for p in range(3):
+        sel = np.nonzero(plane == p)[0]
+        Ap = embed(Af[sel][:, sel].tocsr(), fpos[sel] - p * n3, n3)
+        lvA, PsA = hierarchy(Ap, nsA)
+        refA = cycle(lvA, PsA, ba[p * n3:(p + 1) * n3], gs)
+        errA = np.abs(za[p] - refA).max() / np.abs(refA).max()
+        say(f"    N={N} gs={gs} A plane {p} V-cycle: max rel err {errA:.2e}")
+        assert errA < VC_TOL
+
+
+@pytest.mark.parametrize("N,seed", [(48, 5), (96, 1)])
+def test_coarse_gauss_seidel_and_jacobi_agree(P, N, seed):
+    """Both coarse smoothers give the same outer trajectory (same outer count
+    +-1, same permeability to the inner tolerance's effect)."""
+    m = spheres(N, 4.0, 0.45, seed)
+    res = {}
+    with P.Stokes(m) as s:
+        for gs in (0, 1):
+            s.set_option("mg_coarse_gs", gs)
+            res[gs] = s.solve(P.STOKES_SIMPLE, 1e-8)
+    a, b = res[0], res[1]
+    say(f"    N={N} jacobi: outer={a['outer_iters']} innerA={a['inner_A_iters']} innerS={a['inner_S_iters']}  "
+        f"gs: outer={b['outer_iters']} innerA={b['inner_A_iters']} innerS={b['inner_S_iters']}")
+    assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
+    assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
