@@ -194,13 +194,15 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 (resp. with A) by a geometric multigrid V-cycle, the role the
  *                 paper gives to algebraic multigrid (Sec. 3.2); 0: Jacobi.
  *                 The inner stopping test is the same either way.
- *   "mg_omega", "mg_scale", "mg_coarse_sweeps"  V-cycle smoothing weight
- *                 (0.9), coarse-correction scale (1.7, below 2 keeps it SPD),
- *                 coarsest-level sweeps (16)
+ *   "mg_omega", "mg_scale", "mg_scale_A", "mg_coarse_sweeps"  V-cycle
+ *                 smoothing weight (0.9), coarse-correction scale for the
+ *                 SIMPLE matrix (1.7) and for A (1.5) (below 2 keeps the cycle
+ *                 SPD), coarsest-level damped-Jacobi sweeps (8)
  *   "mg_coarse_gs" 1 (default): coarse levels with a side below 64 (and not
  *                 the coarsest) smooth by symmetric red-black Gauss-Seidel
  *                 (red then black going down, black then red going up);
- *                 0: damped Jacobi with "mg_omega", like the finer levels
+ *                 2: every coarse level but the coarsest; 0: damped Jacobi
+ *                 with "mg_omega", like level 0
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

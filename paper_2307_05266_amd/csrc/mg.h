@@ -374,28 +374,55 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
 // Partials of (r, D^-1 r) and (D^-1 r, D^-1 r) go to the RZ and ZZ slots as the
 // plain update's do.  Sweep: even z-runs and the stencil's block count (its
 // partials are re-added here).
+// The loads of a point (code, the SIMPLE matrix's 1/D, r and q of each plane),
+// apart from the arithmetic that needs alpha, so a kernel can issue its first
+// points' loads before it reduces alpha.
+template <class T, int KIND>
+struct MgfRaw {
+    static constexpr int NB = MgfPt<T, KIND>::NB;
+    int cd;
+    T inv0;
+    T r[NB], q[NB];
+};
+
+template <class T, int KIND>
+__device__ __forceinline__ void mgf_load_upd(MgfRaw<T, KIND>& w, int N, int i, int j, int k,
+                                             const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                                             const T* __restrict__ r, const T* __restrict__ qv) {
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    const int X = i + N * (j + N * k);
+    const size_t n3 = (size_t)N * N * N;
+    w.cd = code[X];
+    w.inv0 = KIND == kMgFineShat ? invd[X] : T(0);
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        w.r[a] = r[a * n3 + X];
+        w.q[a] = qv[a * n3 + X];
+    }
+}
+
+template <class T, int KIND>
+__device__ __forceinline__ void mgf_finish_upd(MgfPt<T, KIND>& q, const MgfRaw<T, KIND>& w, T alpha, T omega,
+                                               const FaceTab<T>& ft) {
+    constexpr int NB = MgfPt<T, KIND>::NB;
+    q.cd = w.cd;
+    if (KIND == kMgFineShat) q.inv[0] = w.inv0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        if (KIND == kMgFineA) q.inv[a] = ft.inv[a][q.cd];
+        q.b[a] = w.r[a] - alpha * w.q[a];
+        q.x[a] = omega * q.inv[a] * q.b[a];
+    }
+}
+
 template <class T, int KIND>
 __device__ __forceinline__ void mgf_point_upd(MgfPt<T, KIND>& q, int N, int i, int j, int k,
                                               const uint8_t* __restrict__ code, const T* __restrict__ invd,
                                               const T* __restrict__ r, const T* __restrict__ qv, T alpha, T omega,
                                               const FaceTab<T>& ft) {
-    constexpr int NB = MgfPt<T, KIND>::NB;
-    const int X = i + N * (j + N * k);
-    const size_t n3 = (size_t)N * N * N;
-    q.cd = code[X];
-    if (KIND == kMgFineShat) q.inv[0] = invd[X];
-    T rv[NB], qq[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-        rv[a] = r[a * n3 + X];
-        qq[a] = qv[a * n3 + X];
-    }
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-        if (KIND == kMgFineA) q.inv[a] = ft.inv[a][q.cd];
-        q.b[a] = rv[a] - alpha * qq[a];
-        q.x[a] = omega * q.inv[a] * q.b[a];
-    }
+    MgfRaw<T, KIND> w;
+    mgf_load_upd<T, KIND>(w, N, i, j, k, code, invd, r, qv);
+    mgf_finish_upd<T, KIND>(q, w, alpha, omega, ft);
 }
 
 template <class T, int KIND>
@@ -405,16 +432,10 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
                                                                 const T* __restrict__ d, const T* __restrict__ q,
                                                                 T* __restrict__ bc, T omega, CgState* st,
                                                                 double* part) {
-    if (st->done) return;
-    double alpha_d;
-    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
-    const T alpha = (T)alpha_d;
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[NB * kBlock / 2];
     __shared__ FaceTab<T> ft;
-    face_tab_fill<T>(ft);
-    __syncthreads();
     const size_t n3 = (size_t)s.n3;
     const Tile tt = tile_of(s);
     const int N = tt.N, W = tt.W, lb = tt.lb;
@@ -422,16 +443,27 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
     const bool valid = tt.valid;
     const int hi = tt.hi, hj = tt.hj, hslot = tt.hslot, own = tt.own;
     auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
+    // the first two planes' loads go out before alpha is reduced (in bounds
+    // whether or not the solve has finished)
+    MgfRaw<T, KIND> wprev, wcur;
+    mgf_load_upd<T, KIND>(wprev, N, wi, wj, zw(k0 - 1), code, invd, r, q);
+    mgf_load_upd<T, KIND>(wcur, N, wi, wj, k0, code, invd, r, q);
+    if (st->done) return;
+    double alpha_d;
+    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
+    const T alpha = (T)alpha_d;
+    face_tab_fill<T>(ft);
+    __syncthreads();
 
     MgfPt<T, KIND> cur, nxt;
     T xprev[NB];
     {
         MgfPt<T, KIND> pv;
-        mgf_point_upd<T, KIND>(pv, N, wi, wj, zw(k0 - 1), code, invd, r, q, alpha, omega, ft);
+        mgf_finish_upd<T, KIND>(pv, wprev, alpha, omega, ft);
 #pragma unroll
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
-    mgf_point_upd<T, KIND>(cur, N, wi, wj, k0, code, invd, r, q, alpha, omega, ft);
+    mgf_finish_upd<T, KIND>(cur, wcur, alpha, omega, ft);
     double acc[2] = {0.0, 0.0};
     T rsum[NB];
 #pragma unroll

@@ -85,6 +85,7 @@ struct stokes_ctx {
     int64_t nface[3] = {0, 0, 0};
 
     Sweep sw{};
+    Sweep sw32{};           // the FP32 inner solves' sweep
     int wpr = 0;            // bitmask words per x-row
 
     // device memory
@@ -124,13 +125,14 @@ struct stokes_ctx {
     MgHier mgS, mgA;
     int use_mg = 1;                    // SIMPLE inner solve: 1 multigrid-PCG, 0 Jacobi-PCG
     int use_mg_A = 1;                  // inner solve with A: 1 multigrid-PCG, 0 Jacobi-PCG
-    double mg_omega = 0.9, mg_scale = 1.7;
+    double mg_omega = 0.9, mg_scale = 1.7, mg_scale_A = 1.5;   // coarse-correction scale: SIMPLE matrix, A
     // multigrid solves: direction fused with the stencil (measured: a gain for
     // the SIMPLE matrix; about even for A, whose fused sweep loads z and d at
     // the ring points of three planes)
     int fuse_dir_A = 0, fuse_dir_S = 1;
-    int mg_coarse_sweeps = 16;
-    // coarse levels below the tiled size: 1 red-black Gauss-Seidel, 0 damped Jacobi
+    int mg_coarse_sweeps = 8;
+    // coarse-level smoother: 0 damped Jacobi; 1 red-black Gauss-Seidel below the
+    // tiled size; 2 red-black Gauss-Seidel on every coarse level but the coarsest
     int mg_coarse_gs = 1;
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
@@ -201,6 +203,21 @@ Sweep make_sweep(int N, int target_blocks) {
     s.nblk = s.gx * s.gy * s.gz;
     return s;
 }
+
+// Sweep of the FP32 inner solves: their kernels hold about half the registers
+// of the FP64 ones and keep twice the waves per SIMD, so they run over up to
+// twice the blocks, as long as a block's z-run keeps at least 8 planes (the
+// first and last plane of a run are loaded twice).
+Sweep make_sweep32(int N, int target_blocks) {
+    const Sweep s = make_sweep(N, target_blocks);
+    const int cols = s.gx * s.gy;
+    const int t = std::min(2 * target_blocks, std::max(target_blocks, cols * std::max(1, N / 8)));
+    return make_sweep(N, std::min(t, kMaxBlocks));
+}
+
+// the sweep of an inner solve in precision T (one for all its kernels)
+const Sweep& inner_sweep(const stokes_ctx* c, double) { return c->sw; }
+const Sweep& inner_sweep(const stokes_ctx* c, float) { return c->sw32; }
 
 template <class T>
 stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
@@ -394,7 +411,7 @@ GraphKey graph_key(int variant, const void* a, const void* b, const void* cc, co
 // and update kernels.
 template <class T>
 stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
-    const Sweep& s = c->sw;
+    const Sweep& s = inner_sweep(c, T());
     CgState* st = c->cg + 0;
     hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
                        c->force[1], c->force[2], v.x, v.r, st, c->part, eps, c->max_inner);
@@ -426,7 +443,7 @@ stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* 
 // Jacobi-preconditioned.
 template <class T>
 stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
-    const Sweep& s = c->sw;
+    const Sweep& s = inner_sweep(c, T());
     CgState* st = c->cg + 1;
     hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
                        eps, c->max_inner);
@@ -574,7 +591,8 @@ template <class T>
 stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st,
                      bool restricted = false) {
     const int L = h.levels;
-    const T omega = (T)c->mg_omega, scale = (T)c->mg_scale;
+    const Sweep& s0 = inner_sweep(c, T());   // level 0: the inner solve's sweep
+    const T omega = (T)c->mg_omega, scale = (T)(h.kind == kMgFineA ? c->mg_scale_A : c->mg_scale);
     std::vector<MgOp> ops(L + 1);
     ops[0] = {c->code, h.kind, invd0, nullptr, nullptr, nullptr, nullptr};
     for (int l = 1; l <= L; ++l) {
@@ -583,6 +601,11 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     }
     auto nodes = [&](int l) { return h.nb * h.grid[l].n3; };
     const bool kindA = h.kind == kMgFineA;
+    // coarse level l (1 <= l < L) smooths by red-black Gauss-Seidel
+    auto use_gs = [&](int l) {
+        const int n = h.grid[l].n;
+        return n >= kGsMinSide && (c->mg_coarse_gs == 2 || (c->mg_coarse_gs == 1 && n < kMgTiledMinSide));
+    };
     // descend: residual of the first Jacobi sweep, restricted (unless the
     // fused CG update already did)
     if (!restricted) {
@@ -591,17 +614,20 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
         bool open;
         ST_TRY(time_begin(c, kindA ? kTimeMgARestrict : kTimeMgSRestrict, &open));
         if (kindA)
-            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, false>), grid_of(c->sw), dim3(kBlock), 0, c->stream,
-                               c->sw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, false>), grid_of(s0), dim3(kBlock), 0, c->stream,
+                               s0, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         else
-            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, false>), grid_of(c->sw), dim3(kBlock), 0, c->stream,
-                               c->sw, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
+            hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, false>), grid_of(s0), dim3(kBlock), 0, c->stream,
+                               s0, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         ST_TRY(time_end(c, open));
     }
     for (int l = 1; l < L; ++l) {
         const T* bl = mg_view(h, l, T()).b;
         T* bn = mg_view(h, l + 1, T()).b;
-        if (h.grid[l].n >= kMgTiledMinSide) {
+        if (use_gs(l)) {
+            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
+        } else if (h.grid[l].n >= kMgTiledMinSide) {
             const Sweep& ls = h.sweep[l];
             if (kindA)
                 hipLaunchKernelGGL((k_mgc_tiled<T, 3, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
@@ -609,9 +635,6 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
             else
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
-        } else if (c->mg_coarse_gs && h.grid[l].n >= kGsMinSide) {
-            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
-                               h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
         } else {
             hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0,
                                c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
@@ -628,7 +651,10 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     auto coarse_x = [&](int l) -> const T* { return l == L ? mg_view(h, L, T()).x : mg_view(h, l, T()).y; };
     for (int l = L - 1; l >= 1; --l) {
         auto v = mg_view(h, l, T());
-        if (h.grid[l].n >= kMgTiledMinSide) {
+        if (use_gs(l)) {
+            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, v.y, st);
+        } else if (h.grid[l].n >= kMgTiledMinSide) {
             const Sweep& ls = h.sweep[l];
             if (kindA)
                 hipLaunchKernelGGL((k_mgc_tiled<T, 3, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
@@ -636,9 +662,6 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
             else
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
-        } else if (c->mg_coarse_gs && h.grid[l].n >= kGsMinSide) {
-            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
-                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, v.y, st);
         } else {
             hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream,
                                h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y,
@@ -648,10 +671,10 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     bool open;
     ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : kTimeMgSSmooth, &open));
     if (kindA)
-        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
     else
-        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw,
+        hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
     ST_TRY(time_end(c, open));
     HIP_TRY(hipGetLastError());
@@ -663,7 +686,7 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
 // direction, stencil, update, then the V-cycle that forms the next z.
 template <class T>
 stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int* iters, int* status) {
-    const Sweep& s = c->sw;
+    const Sweep& s = inner_sweep(c, T());
     CgState* st = c->cg + 1;
     T* z = mg_out(c->mgS, T());
     hipLaunchKernelGGL(k_cgS_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, v.invd, b, v.x, v.r, st, c->part,
@@ -714,7 +737,7 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
 // Jacobi-scaled residual as in the plain solve.
 template <class T>
 stokes_status cg_A_mg(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int* iters, int* status) {
-    const Sweep& s = c->sw;
+    const Sweep& s = inner_sweep(c, T());
     CgState* st = c->cg + 0;
     T* z = mg_out(c->mgA, T());
     hipLaunchKernelGGL(k_cgA_init<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, b, c->force[0],
@@ -916,10 +939,11 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
 
     const int N = c->N;
     const int64_t n3 = c->n3;
-    // one sweep for every kernel (the fused update and restriction re-adds the
-    // stencil's partials, so both need one block count)
+    // one sweep for every kernel of an inner solve (the fused update and
+    // restriction re-adds the stencil's partials, so both need one block count)
     c->sw = make_sweep(N, c->sweep_blocks);
-    if (c->sw.nblk > kMaxBlocks) return STOKES_E_LIMIT;
+    c->sw32 = make_sweep32(N, c->sweep_blocks);
+    if (c->sw.nblk > kMaxBlocks || c->sw32.nblk > kMaxBlocks) return STOKES_E_LIMIT;
     c->wpr = (N + 31) / 32;
 
     // remaining-fluid bitmask
@@ -1146,14 +1170,17 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "mg_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_mg_A = (int)v; }
     else if (k == "mg_omega") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->mg_omega = v; }
     else if (k == "mg_scale") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale = v; }
+    else if (k == "mg_scale_A") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale_A = v; }
     else if (k == "mg_coarse_sweeps") { if (v < 1 || v > 1000) return STOKES_E_ARG; c->mg_coarse_sweeps = (int)v; }
-    else if (k == "mg_coarse_gs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->mg_coarse_gs = (int)v; }
+    else if (k == "mg_coarse_gs") { if (v != 0.0 && v != 1.0 && v != 2.0) return STOKES_E_ARG; c->mg_coarse_gs = (int)v; }
     else if (k == "sweep_blocks") {
         if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
         const Sweep sw = make_sweep(c->N, (int)v);
-        if (sw.nblk > kMaxBlocks) return STOKES_E_ARG;
+        const Sweep sw32 = make_sweep32(c->N, (int)v);
+        if (sw.nblk > kMaxBlocks || sw32.nblk > kMaxBlocks) return STOKES_E_ARG;
         c->sweep_blocks = (int)v;
         c->sw = sw;
+        c->sw32 = sw32;
     }
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "fuse_dir_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_A = (int)v; }
