@@ -203,6 +203,8 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 (red then black going down, black then red going up);
  *                 2: every coarse level but the coarsest; 0: damped Jacobi
  *                 with "mg_omega", like level 0
+ *   "mg_level_blocks" workgroups a tiled coarse-level sweep aims for (levels
+ *                 with a side of 64 or more; default 1024)
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

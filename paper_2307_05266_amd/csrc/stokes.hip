@@ -72,6 +72,10 @@ constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,     6 * 8 + 1,         
 
 }  // namespace
 
+// tiled coarse-level sweeps: 1 024 blocks (measured: 256 left the 64^3 and 128^3
+// levels latency-bound, 2 048 and 4 096 gain nothing more)
+constexpr int kMgLevelBlocksDefault = 1024;
+
 struct stokes_ctx {
     int N = 0;
     int64_t n3 = 0;
@@ -134,6 +138,7 @@ struct stokes_ctx {
     // coarse-level smoother: 0 damped Jacobi; 1 red-black Gauss-Seidel below the
     // tiled size; 2 red-black Gauss-Seidel on every coarse level but the coarsest
     int mg_coarse_gs = 1;
+    int mg_level_blocks = kMgLevelBlocksDefault;   // target blocks of a tiled coarse-level sweep
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -490,10 +495,9 @@ unsigned gs_blocks(const MgGrid& g) {
 // Levels: halve while the side is even and a level holds more than 512 nodes
 // per plane; the coarsest level must fit one workgroup's LDS.
 // Coarse levels with a side of at least this run the LDS-tiled kernels (over a
-// sweep of about kMgLevelBlocks blocks); smaller ones are launch-latency bound
-// and keep one thread per node.
+// sweep of about "mg_level_blocks" blocks); smaller ones are launch-latency
+// bound and run the brick or one-thread-per-node kernels.
 constexpr int kMgTiledMinSide = 64;
-constexpr int kMgLevelBlocks = 256;
 
 // Sides of the levels of a hierarchy with nb planes on an N^3 box (level 0
 // first); a single entry when there is no hierarchy.
@@ -516,7 +520,7 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     h.sweep.clear();
     for (int n : mg_plan(c->N, nb)) {
         h.grid.push_back({n, n * n, n * n * n, nb});
-        h.sweep.push_back(make_sweep(n, kMgLevelBlocks));
+        h.sweep.push_back(make_sweep(n, c->mg_level_blocks));
     }
     const int L = (int)h.grid.size() - 1;
     if (L < 1) return STOKES_OK;
@@ -1172,6 +1176,12 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "mg_scale") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale = v; }
     else if (k == "mg_scale_A") { if (!(v > 0.0 && v <= 2.0)) return STOKES_E_ARG; c->mg_scale_A = v; }
     else if (k == "mg_coarse_sweeps") { if (v < 1 || v > 1000) return STOKES_E_ARG; c->mg_coarse_sweeps = (int)v; }
+    else if (k == "mg_level_blocks") {
+        if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
+        c->mg_level_blocks = (int)v;
+        for (MgHier* h : {&c->mgS, &c->mgA})
+            for (size_t l = 0; l < h->sweep.size(); ++l) h->sweep[l] = make_sweep(h->grid[l].n, c->mg_level_blocks);
+    }
     else if (k == "mg_coarse_gs") { if (v != 0.0 && v != 1.0 && v != 2.0) return STOKES_E_ARG; c->mg_coarse_gs = (int)v; }
     else if (k == "sweep_blocks") {
         if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
