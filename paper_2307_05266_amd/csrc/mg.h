@@ -16,12 +16,15 @@
 // to the neighbouring block.
 //
 // V-cycle (symmetric, hence a valid CG preconditioner): on each level one
-// damped-Jacobi sweep from zero, residual restricted to the next level,
-// coarse correction prolonged and scaled, one damped-Jacobi sweep; the
-// coarsest level runs a fixed number of Jacobi sweeps inside one workgroup.
-// Scaling the coarse correction (by less than 2) keeps the cycle SPD and
-// offsets the weak coarse operators of piecewise-constant aggregation.
-// Nodes that are not unknowns (diagonal 0) are held at 0.
+// smoothing step from zero, residual restricted to the next level, coarse
+// correction prolonged and scaled, one smoothing step; the smoothing step is a
+// damped-Jacobi sweep on level 0 and on the tiled coarse levels, and a
+// red-black Gauss-Seidel sweep (red then black going down, black then red
+// going up) on the smaller coarse levels; the coarsest level runs a fixed
+// number of Jacobi sweeps inside one workgroup.  Scaling the coarse correction
+// (by less than 2) keeps the cycle SPD and offsets the weak coarse operators
+// of piecewise-constant aggregation.  Nodes that are not unknowns (diagonal 0)
+// are held at 0.
 #pragma once
 
 #include "kernels.h"
@@ -659,15 +662,14 @@ __device__ __forceinline__ GsBrick gs_brick(const MgGrid& g) {
     return r;
 }
 
-// Window point (wx, wy, wz) is global node o + w - 2, wrapped (the side is at
-// least 10, so one wrap suffices).
-
 // Row of one node: b, D, 1/D and the couplings to -x, +x, -y, +y, -z, +z
 template <class T>
 struct GsRow {
     T b, d, inv, w[6];
 };
 
+// the row of window point (wx, wy, wz), which is global node o + w - 2, wrapped
+// (the side is at least 10, so one wrap suffices)
 template <class T>
 __device__ __forceinline__ void gs_row(GsRow<T>& r, const MgGrid& g, const MgOp& op, const T* __restrict__ b,
                                        const GsBrick& k, int wx, int wy, int wz) {
@@ -839,7 +841,7 @@ __global__ void __launch_bounds__(kGsThreads) k_mgc_gs_postsmooth(MgGrid g, MgOp
     }
 }
 
-// Levels >= 1 with a side of at least 32, LDS-tiled like level 0: the
+// Levels >= 1 with a side of at least 64, LDS-tiled like level 0: the
 // smoothed iterate (x0 = omega D^-1 b, plus scale P xc when smoothing) once per
 // point, own column k-1, k, k+1 in registers, plane k plus a ring in LDS.  The
 // couplings to +x and +y are read from the neighbour's W^x, W^y; the one to +z
