@@ -45,8 +45,50 @@ WORKLOADS = {
 }
 
 
+# `--study precond`: SIMPLE against Uzawa over surface-to-volume ratios at 128^3
+# (the paper's Sec. 4.1.2 / 4.2.2 comparison).  Plane channels parallel to the
+# force carry no pressure: there g = B A^-1 f is only the inner solve's error,
+# so their outer counts measure iterations on that noise, not the preconditioner.
+PRECOND_STUDY = [
+    ("spheres r=10 porosity 0.7 seed 0", lambda: __import__("synth").spheres(128, 10.0, 0.7, 0)),
+    ("spheres r=6 porosity 0.5 seed 0", lambda: __import__("synth").spheres(128, 6.0, 0.5, 0)),
+    ("spheres r=4 porosity 0.4 seed 0", lambda: __import__("synth").spheres(128, 4.0, 0.4, 0)),
+    ("spheres r=3 porosity 0.3 seed 0", lambda: __import__("synth").spheres(128, 3.0, 0.3, 0)),
+    ("spheres r=3 porosity 0.2 seed 0", lambda: __import__("synth").spheres(128, 3.0, 0.2, 0)),
+    ("slit stack, walls 2, widths 4 8 12 16 24 32, walls normal to y",
+     lambda: __import__("synth").slits(128, [4, 8, 12, 16, 24, 32], 2, 1)),
+]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def precond_study(P):
+    """One JSON line per geometry: outer iterations, inner iterations and solve
+    time of the FP64 solve (tol 1e-8) with each preconditioner."""
+    import torch
+    for desc, gen in PRECOND_STUDY:
+        mask = gen()
+        with P.Stokes(mask, (1.0, 0.0, 0.0)) as s:
+            s.set_option("progress", 250)              # Uzawa may take thousands of outer iterations
+            info = s.info()
+            row = {"study": "precond", "geometry": desc, "N": info["N"],
+                   "porosity": info["nfluid_in"] / info["N"] ** 3,
+                   "stv_ratio": info["nsurf"] / max(1, info["nfluid_in"])}
+            for name, pc in (("simple", P.STOKES_SIMPLE), ("uzawa", P.STOKES_UZAWA)):
+                s.solve(pc, 1e-8)                      # graphs captured, caches warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rep = s.solve(pc, 1e-8)
+                dt = time.perf_counter() - t0
+                row[name] = {"outer_iters": rep["outer_iters"], "inner_A_iters": rep["inner_A_iters"],
+                             "inner_S_iters": rep["inner_S_iters"], "seconds": dt, "k_hat": rep["k_hat"],
+                             "status": rep["status"]}
+                log(f"[study] {desc}: {name} outer={rep['outer_iters']} {dt:.3f} s k={rep['k_hat']:.10e}")
+            ks, ku = row["simple"]["k_hat"], row["uzawa"]["k_hat"]
+            row["k_rel_diff"] = abs(ks - ku) / abs(ks) if ks else 0.0
+        print(json.dumps(row), flush=True)
 
 
 def measured_traffic(kernel, N):
@@ -207,6 +249,8 @@ def main():
                     help="serving requests run beside the solve benchmark (0 = skip)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
+    ap.add_argument("--study", choices=["precond"],
+                    help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this solver has no multi-GPU path",
@@ -214,7 +258,7 @@ def main():
         sys.exit(2)
     # one hardware queue per server slot; read when the process first uses HIP
     os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, args.serve_slots)))
-    reqs = generate_requests(args.requests)
+    reqs = generate_requests(args.requests) if not args.study else []
 
     import torch
 
@@ -224,6 +268,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.load()
+    if args.study == "precond":
+        precond_study(P)
+        return
     if args.serve_only:
         sv = serve(P, reqs, slots=args.serve_slots)
         out = {"metric": "permeability solves/s (serving)", "value": sv["throughput_requests_per_s"],
