@@ -440,10 +440,6 @@ stokes_status cg_A(stokes_ctx* c, InnerA<T> v, const double* b, double eps, int*
     return run_inner(c, 0, graph_key<T>(0, v.x, v.r, v.d, v.q, nullptr, nullptr), body, iters, status);
 }
 
-stokes_status cg_A(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
-    return cg_A<double>(c, bufA64(c), b, eps, iters, status);
-}
-
 // Solve Shat x = b on the cells (b: an FP64 cell vector, already projected),
 // Jacobi-preconditioned.
 template <class T>
@@ -470,10 +466,6 @@ stokes_status cg_S(stokes_ctx* c, InnerS<T> v, const double* b, double eps, int*
         return STOKES_OK;
     };
     return run_inner(c, 1, graph_key<T>(1, v.x, v.r, v.d, v.q, v.invd, nullptr), body, iters, status);
-}
-
-stokes_status cg_S(stokes_ctx* c, const double* b, double eps, int* iters, int* status) {
-    return cg_S<double>(c, bufS64(c), b, eps, iters, status);
 }
 
 // ---- multigrid preconditioners ---------------------------------------------
