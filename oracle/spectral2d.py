@@ -168,13 +168,15 @@ def operators_2d_sparse(m: np.ndarray):
     return A, B
 
 
-def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10000):
+def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10000, coeffs: list = None):
     """Outer PCG on S p = g (Algorithm 1 with the standard signs) for a unit
     force along x, inner solves with A and with the SIMPLE matrix done by sparse
     LU (so the inner solves are exact to rounding, the paper's tight inner
     tolerance), stopping on the unpreconditioned relative residual ||r|| / ||r0||
     as in the paper's 2D runs.  Returns (iterations, permeability per pixel of
-    the box, ||r|| / ||r0|| at exit); the fluid must form one component."""
+    the box, ||r|| / ||r0|| at exit); the fluid must form one component.  If
+    `coeffs` is a list, the (alpha, beta) pairs of the iterations are appended
+    to it (for the Lanczos estimate of the spectrum seen by g)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as sla
     A, B = operators_2d_sparse(m)
@@ -223,10 +225,15 @@ def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10
         r -= r.mean()
         k += 1
         if np.linalg.norm(r) / rn0 < tol:
+            if coeffs is not None:
+                coeffs.append((alpha, 0.0))
             break
         z = M(r)
         rz_new = r @ z
-        d = z + (rz_new / rz) * d
+        beta = rz_new / rz
+        if coeffs is not None:
+            coeffs.append((alpha, beta))
+        d = z + beta * d
         rz = rz_new
     u = luA.solve(f - B.T @ p)
     return k, float(u[:nx].sum() / n ** 2), float(np.linalg.norm(r) / rn0)
@@ -312,9 +319,22 @@ def study(cases, out=None):
 
 
 # The paper's 2D channel-width sweep (Sec. 4.2.2, table tab:2d_avg_summary):
-# n_avg -> (sigma_s %, Uzawa iterations, SIMPLE iterations) as printed in its
-# main table; its appendix table lists each count one lower.
-PAPER_2D_SWEEP = {4: (46.9, 138, 15), 6: (30.5, 98, 22), 8: (22.3, 81, 29), 10: (17.3, 61, 35), 12: (14.0, 52, 40)}
+# n_avg -> (sigma_s %, Uzawa iterations, SIMPLE iterations, cond(S),
+# cond of the SIMPLE-preconditioned S) as printed in its main table; its
+# appendix table lists each count one lower.
+PAPER_2D_SWEEP = {4: (46.9, 138, 15, 4.7e3, 34), 6: (30.5, 98, 22, 2.3e3, 86), 8: (22.3, 81, 29, 1.3e3, 160),
+                  10: (17.3, 61, 35, 7.7e2, 260), 12: (14.0, 52, 40, 5.3e2, 340)}
+
+
+def lanczos_cond_2d(m: np.ndarray, precond: str, tol: float = 1e-12):
+    """Condition number of S (Uzawa) or of the SIMPLE-preconditioned S as seen
+    by g: extreme Ritz values of the CG tridiagonal of a tight solve (Saad,
+    Sec. 6.7.3), a lower bound of the full condition number."""
+    from oracle import lanczos_ritz
+    c = []
+    schur_pcg_2d(m, precond, tol=tol, coeffs=c)
+    rz = lanczos_ritz([a for a, _ in c], [b for _, b in c])
+    return float(rz.max() / rz.min())
 
 
 def iteration_sweep(n_avgs=(4, 6, 8, 10, 12), seeds=range(10), N=7, n_c=50, n_min=2, out=None):
@@ -333,8 +353,12 @@ def iteration_sweep(n_avgs=(4, 6, 8, 10, 12), seeds=range(10), N=7, n_c=50, n_mi
                 res[pc].append(k)
                 ks[pc] = perm
             res["kdiff"].append(abs(ks["simple"] - ks["uzawa"]) / ks["simple"])
+        m0 = squares_2d(N, n_c, navg, n_min, list(seeds)[0])
+        res["cond_S"] = lanczos_cond_2d(m0, "uzawa")
+        res["cond_simple"] = lanczos_cond_2d(m0, "simple")
         rows.append((navg, res))
-        print(navg, {k: (float(np.mean(v)), min(v), max(v)) for k, v in res.items()}, flush=True)
+        print(navg, {k: (float(np.mean(v)), min(v), max(v)) if isinstance(v, list) else v for k, v in res.items()},
+              flush=True)
     if out:
         L = ["# 2D channel-width sweep: outer iterations of Uzawa and SIMPLE on the paper's square arrays", "",
              "Command (repository root): `python -m oracle.spectral2d --iterations`", "",
@@ -342,15 +366,19 @@ def iteration_sweep(n_avgs=(4, 6, 8, 10, 12), seeds=range(10), N=7, n_c=50, n_mi
              f"channel width n_avg on average and at least {n_min} (Sec. 4.2.1), unit force along x, outer PCG on S "
              "to 1e-3 on the unpreconditioned relative residual, inner solves with A and with the SIMPLE matrix by "
              "sparse LU (exact to rounding), as in the paper's 2D runs (Sec. 4.2.2). "
-             f"{len(list(seeds))} seeds per width; iterations counted as applications of S in the loop.", "",
+             f"{len(list(seeds))} seeds per width; iterations counted as applications of S in the loop. "
+             "Condition numbers: Lanczos estimates (extreme Ritz values of a solve to 1e-12) on the first seed's "
+             "geometry (a lower bound of the exact value on that geometry; the paper's are exact on its own draws).", "",
              "| n_avg | sigma_s % (paper) | Uzawa mean [min, max] | paper Uzawa (main / appendix) | "
-             "SIMPLE mean [min, max] | paper SIMPLE (main / appendix) | k relative difference Uzawa vs SIMPLE |",
-             "|---|---|---|---|---|---|---|"]
+             "SIMPLE mean [min, max] | paper SIMPLE (main / appendix) | cond(S) (paper) | "
+             "cond SIMPLE-preconditioned (paper) | k relative difference Uzawa vs SIMPLE |",
+             "|---|---|---|---|---|---|---|---|---|"]
         for navg, r in rows:
-            ps, pu, pm = PAPER_2D_SWEEP.get(navg, (float("nan"), 0, 0))
+            ps, pu, pm, pcs, pcm = PAPER_2D_SWEEP.get(navg, (float("nan"), 0, 0, float("nan"), float("nan")))
             L.append(f"| {navg} | {np.mean(r['sigma']):.1f} ({ps}) | {np.mean(r['uzawa']):.1f} "
                      f"[{min(r['uzawa'])}, {max(r['uzawa'])}] | {pu} / {pu - 1} | {np.mean(r['simple']):.1f} "
-                     f"[{min(r['simple'])}, {max(r['simple'])}] | {pm} / {pm - 1} | {max(r['kdiff']):.1e} |")
+                     f"[{min(r['simple'])}, {max(r['simple'])}] | {pm} / {pm - 1} | {r['cond_S']:.3g} ({pcs:.2g}) | "
+                     f"{r['cond_simple']:.3g} ({pcm:.3g}) | {max(r['kdiff']):.1e} |")
         inside = all(min(r["uzawa"]) <= PAPER_2D_SWEEP[navg][1] - 1 and PAPER_2D_SWEEP[navg][1] <= max(r["uzawa"])
                      and min(r["simple"]) <= PAPER_2D_SWEEP[navg][2] - 1 <= max(r["simple"])
                      for navg, r in rows if navg in PAPER_2D_SWEEP)

@@ -112,3 +112,17 @@ def test_outer_iterations_trend_small():
     s_n, u_n = schur_pcg_2d(narrow, "simple")[0], schur_pcg_2d(narrow, "uzawa")[0]
     s_w, u_w = schur_pcg_2d(wide, "simple")[0], schur_pcg_2d(wide, "uzawa")[0]
     assert s_n < s_w and u_n > u_w and s_n < u_n
+
+
+def test_lanczos_condition_estimate_against_dense_spectra():
+    """The Lanczos estimate from the outer PCG's coefficients (a lower bound:
+    it sees the eigenvalues g excites) against the dense spectra: equal for S
+    on this geometry, within a few per cent for the SIMPLE-preconditioned S."""
+    from oracle.spectral2d import lanczos_cond_2d
+    m = squares_2d(2, 14, 6, 2, 3)
+    ev, evp = schur_spectra(m)
+    nz = ev[np.abs(ev) > 1e-10]
+    c_s, c_p = nz.max() / nz.min(), evp.max() / evp.min()
+    assert lanczos_cond_2d(m, "uzawa", tol=1e-13) == pytest.approx(c_s, rel=1e-6)
+    est = lanczos_cond_2d(m, "simple", tol=1e-13)
+    assert 0.95 * c_p <= est <= c_p * (1 + 1e-9)
