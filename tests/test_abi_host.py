@@ -123,3 +123,17 @@ def test_estimate_bytes_host_only(P):
     for bad in [(1, 0, 0), (801, 0, 0), (32, 2, 0), (32, 0, 2)]:
         with pytest.raises(StokesError):
             P.stokes_estimate_bytes(bad[0], precision=bad[2], flags=bad[1])
+
+
+def test_binding_constants_match_the_header(P):
+    """Every enumerator of include/stokes.h (status codes, preconditioners,
+    operators) has the same value in the Python binding."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADERS[0]).read(), flags=re.S)
+    found = {}
+    for body in re.findall(r"typedef\s+enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(STOKES_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            found[name] = int(val)
+    assert {"STOKES_OP_MG_SHAT", "STOKES_OP_MG_A", "STOKES_SIMPLE", "STOKES_E_LIMIT"} <= set(found)
+    from paper_2307_05266_amd import stokes as B
+    for name, val in found.items():
+        assert getattr(B, name) == val, name
