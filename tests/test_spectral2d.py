@@ -126,3 +126,38 @@ def test_lanczos_condition_estimate_against_dense_spectra():
     assert lanczos_cond_2d(m, "uzawa", tol=1e-13) == pytest.approx(c_s, rel=1e-6)
     est = lanczos_cond_2d(m, "simple", tol=1e-13)
     assert 0.95 * c_p <= est <= c_p * (1 + 1e-9)
+
+
+def _paper_table():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_2d_sweep.json")) as fh:
+        return json.load(fh)
+
+
+def test_paper_2d_sigma_s_reproduced():
+    """sigma_s of the paper's 2D arrays depends only on the channel width for
+    this construction; it matches every printed value to the printed digit."""
+    t = _paper_table()
+    for navg, sig in zip(t["n_avg"], t["sigma_s_percent"]):
+        m = squares_2d(7, 50, navg, 2, 0)
+        assert round(100.0 * surface_pixels(m) / int(m.sum()), 1) == pytest.approx(sig, abs=0.051)
+
+
+@pytest.mark.parametrize("idx", [0, 4])
+def test_paper_2d_outer_counts_in_band(idx):
+    """At the paper's size, one seed: SIMPLE within 3 of the paper's appendix
+    count (which counts iterations as this code does), Uzawa within 20 % of its
+    count (Uzawa varies more from one random draw to the next)."""
+    from oracle.spectral2d import PAPER_2D_SWEEP, schur_pcg_2d
+    t = _paper_table()
+    navg = t["n_avg"][idx]
+    # the oracle's copy of the table (used for the written profile) is the same
+    assert PAPER_2D_SWEEP[navg][:5] == (t["sigma_s_percent"][idx], t["uzawa_iterations"][idx],
+                                        t["simple_iterations"][idx], t["cond_S"][idx],
+                                        t["cond_simple_preconditioned"][idx])
+    m = squares_2d(7, 50, navg, 2, 0)
+    k_s = schur_pcg_2d(m, "simple")[0]
+    k_u = schur_pcg_2d(m, "uzawa")[0]
+    assert abs(k_s - (t["simple_iterations"][idx] - 1)) <= 3
+    assert abs(k_u - t["uzawa_iterations"][idx]) <= 0.2 * t["uzawa_iterations"][idx]
