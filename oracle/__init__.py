@@ -191,10 +191,10 @@ class Oracle:
 
     # ---- the solve ------------------------------------------------------------
     def solve(self, precond=SIMPLE, tol=1e-8, eps_A=1e-12, eps_S=1e-12, max_outer=2000,
-              max_inner=200000, stop_prec=False, true_u=False, hist_cap=4000):
+              max_inner=200000, stop_prec=False, true_u=False, hist_cap=4000, zero_rhs_factor=1000.0):
         N = self.N
         params = np.array([tol, eps_A, eps_S, max_outer, max_inner, int(stop_prec),
-                           int(true_u)], dtype=np.float64)
+                           int(true_u), zero_rhs_factor], dtype=np.float64)
         p = np.zeros(N ** 3)
         u = np.zeros(3 * N ** 3)
         stats = np.zeros(24)
@@ -211,6 +211,7 @@ class Oracle:
             "r0": stats[9], "z0": stats[10],
             "k_hat_true": stats[11], "div_true": stats[12],
             "mean_u": stats[13:16].copy(), "seconds": stats[16], "threads": int(stats[17]),
+            "zero_rhs": bool(stats[18]), "f_dot_u0": stats[19],
             "hist": h.copy(),
             "p": p.reshape(N, N, N), "u": u.reshape(3, N, N, N),
         }

@@ -664,12 +664,18 @@ int oracle_apply(const osys_t *s, int op, const double *in, double *out)
 /* params[4] max_inner                                                    */
 /* params[5] stop_prec  0: ||r||/||r0|| < tol; 1: ||z||/||z0|| < tol      */
 /* params[6] true_u     1: also recompute u = A^{-1}(f - B^T p)           */
+/* params[7] zero_rhs_factor  g = B u0 counts as zero when ||g|| <=       */
+/*           zero_rhs_factor * eps_A * sqrt(f . u0): since S has no       */
+/*           eigenvalue above 1 (Sec. 4.2.2), an exact g obeys            */
+/*           ||g||^2 <= f . A^{-1} f, and an inner residual r_A moves g   */
+/*           by at most ||A^{-1/2} r_A||; below the floor g is the inner  */
+/*           solve's error (channels along the force, exact g = 0)        */
 /*                                                                        */
 /* stats (double[24]):                                                    */
 /*  0 k_hat  1 k_vox  2 outer  3 inner_A  4 inner_S  5 rel_res            */
 /*  6 rel_res_prec  7 ||B u|| (recursive u)  8 status  9 ||r0||  10 ||z0||*/
 /*  11 k_hat (true u)  12 ||B u_true||  13..15 mean velocity (voxel units)*/
-/*  16 seconds  17 threads                                                */
+/*  16 seconds  17 threads  18 1 when g counted as zero  19 f . u0      */
 /* hist (double[hist_cap][8]) per outer iteration k = 1..:                */
 /*  ||r_k||/||r_0||, ||z_k||/||z_0||, k_hat(u_k), inner A, inner S,       */
 /*  alpha_{k-1}, beta_{k-1} (0 when the loop stopped first), unused       */
@@ -698,6 +704,7 @@ int oracle_solve(const osys_t *s, int precond, const double *params,
     const double tol = params[0], epsA = params[1], epsS = params[2];
     const int max_outer = (int)params[3], max_inner = (int)params[4];
     const int stop_prec = (int)params[5], true_u = (int)params[6];
+    const double zero_rhs_factor = params[7];
     const double N2 = (double)s->N * (double)s->N;
     int status = 0, inner_st = 0;
     long innerA = 0, innerS = 0;
@@ -739,8 +746,10 @@ int oracle_solve(const osys_t *s, int precond, const double *params,
     double rz = dot(nc, r, z);
     double r0 = nrm2(nc, r), z0 = nrm2(nc, z);
     double rel = 0.0, relz = 0.0;
+    double fu0 = dot(nf, f, u);
+    double g_floor = fu0 > 0.0 ? zero_rhs_factor * epsA * sqrt(fu0) : 0.0;
     int k = 0;
-    if (r0 > 0.0) {
+    if (r0 > g_floor) {
         for (k = 0; k < max_outer;) {
             long ia0 = innerA, is0 = innerS;
             spmv(&s->BT, d, w);                                 /* w = B^T d */
@@ -793,6 +802,8 @@ int oracle_solve(const osys_t *s, int precond, const double *params,
     stats[8] = status;
     stats[9] = r0;
     stats[10] = z0;
+    stats[18] = r0 > g_floor ? 0.0 : 1.0;
+    stats[19] = fu0;
     stats[13] = mean[0]; stats[14] = mean[1]; stats[15] = mean[2];
     if (true_u) {
         /* u_true = A^{-1}(f - B^T p) */

@@ -40,4 +40,7 @@ from .stokes import (  # noqa: F401
     STOKES_OP_S,
     STOKES_OP_MG_SHAT,
     STOKES_OP_MG_A,
+    STOKES_FLAG_NO_FLOW,
+    STOKES_FLAG_ZERO_RHS,
+    STOKES_FLAG_INNER_MAXIT,
 )

@@ -157,6 +157,8 @@ struct stokes_ctx {
     double cycle_rtol = 1e-4;      // residual reduction per defect-correction cycle
     double eps_refine = 1e-12;     // FP64 velocity refinement tolerance
     int max_refine = 12;
+    // g counts as zero below zero_rhs_factor * eps * sqrt(f . u0) (rhs_floor)
+    double zero_rhs_factor = 1000.0;
 
     // options
     double eps_A = 1e-12, eps_S = 1e-12;
@@ -1162,6 +1164,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "eps_S32") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_S32 = v; }
     else if (k == "cycle_rtol") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->cycle_rtol = v; }
     else if (k == "eps_refine") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_refine = v; }
+    else if (k == "zero_rhs_factor") { if (!(v >= 0.0 && v <= 1e12)) return STOKES_E_ARG; c->zero_rhs_factor = v; }
     else if (k == "mg") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_mg = (int)v; }
     else if (k == "mg_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_mg_A = (int)v; }
     else if (k == "mg_omega") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->mg_omega = v; }
@@ -1193,6 +1196,24 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
 }
 
 static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double tol);
+
+// Level below which the right-hand side g = B u0, u0 = A^{-1} f, is taken to be
+// zero.  S = B A^{-1} B^T has no eigenvalue above 1 (Sec. 4.2.2, eq.
+// lambda_cg_rate), so ||B A^{-1/2}|| <= 1: an inner-solve residual r_A perturbs
+// g by at most ||A^{-1/2} r_A||, and an exact g obeys
+// ||g||^2 <= g^T S^+ g <= f^T A^{-1} f = f . u0 (the energy of the exact flow,
+// f . u = f^T A^{-1} f - g^T S^+ g, is not negative).  With u0 accurate to the relative
+// inner tolerance eps, a g below zero_rhs_factor * eps * sqrt(f . u0) cannot
+// be told from the inner solve's error (straight channels along the force,
+// whose exact g is 0); the pressure is then zero and u = u0.
+static stokes_status rhs_floor(stokes_ctx* c, double eps, double* floor_out) {
+    double sums[3];
+    ST_TRY(face_sums(c, c->u, sums));
+    double fu = 0.0;
+    for (int a = 0; a < 3; ++a) fu += c->force[a] * sums[a];
+    *floor_out = fu > 0.0 ? c->zero_rhs_factor * eps * std::sqrt(fu) : 0.0;
+    return STOKES_OK;
+}
 
 // one line on stderr every `progress` outer iterations (option "progress")
 static void report_progress(stokes_ctx* c, int k, double rel, double k_hat) {
@@ -1241,6 +1262,8 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
     totA += itA;
     note_inner(stA);
     std::swap(c->u, c->fx);
+    double g_floor = 0.0;
+    ST_TRY(rhs_floor(c, c->eps_A, &g_floor));
     // r0 = g - S 0 = B u0
     hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
     HIP_TRY(hipGetLastError());
@@ -1263,7 +1286,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
     std::vector<double> alphas, betas;
     int k = 0;
     double rel = 0.0, relz = 0.0;
-    if (!(r0 > 0.0)) {
+    if (!(r0 > g_floor)) {
         R.flags |= STOKES_FLAG_ZERO_RHS;
     } else {
         while (status >= 0) {
@@ -1428,6 +1451,8 @@ static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double t
     int inner_status = 0, status = STOKES_OK;
     HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
     ST_TRY(refine_velocity(c, &totA, &inner_status));
+    double g_floor = 0.0;
+    ST_TRY(rhs_floor(c, c->eps_refine, &g_floor));
     hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
     HIP_TRY(hipGetLastError());
     ST_TRY(project(c, c->r));
@@ -1439,7 +1464,7 @@ static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double t
     int k = 0;
     int cycle = 0;
     std::vector<double> alphas, betas;   // first cycle only: a restart starts a new Krylov space
-    if (!(r0 > 0.0)) {
+    if (!(r0 > g_floor)) {
         R.flags |= STOKES_FLAG_ZERO_RHS;
     } else {
         bool done = false;

@@ -7,7 +7,7 @@ permeability against the FP64 GPU solve of the same geometry (bar 1e-4).
 - 256^3 overlapping spheres r = 3, porosity 0.2 (surface-to-volume above the
   paper's range; ~43 k components, one conducts), SIMPLE, mixed and FP64;
 - 512^3 Gaussian random field, correlation length 8, porosity 0.15, SIMPLE,
-  mixed (about two minutes; marked `long`).
+  mixed (about two minutes; marked `long`, which selects it but does not skip it).
 """
 
 import sys

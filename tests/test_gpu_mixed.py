@@ -86,12 +86,24 @@ def test_mixed_slit_closed_form(P):
 def test_mixed_oblique_slits(P):
     N = 48
     m = slits(N, [3, 4, 6], axis=1)
-    with P.Stokes(m, (1.0, 0.5, 0.0), precision=1) as s:
+    force = (1.0, 0.5, 0.0)
+    with P.Stokes(m, force, precision=1) as s:
         rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+        p, u = s.fields()
     ws = channel_widths(N, [3, 4, 6])
     assert rep["mean_u"][0] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-8)
-    # u_y vanishes in the exact solution; the solve leaves it at the outer tolerance's level
-    assert abs(rep["mean_u"][1]) < 10 * 1e-8 * rep["mean_u"][0]
+    # u_y vanishes in the exact solution.  Discretely, the sum of B u over one
+    # y-row of a channel (all x, z) telescopes to the difference of the y-fluxes
+    # through the two planes bounding it (x and z terms cancel by periodicity),
+    # and no flux crosses a wall, so the y-flux through any plane of a channel is
+    # a partial sum of B u over the rows between that plane and a wall.  Hence
+    # |sum of u_y| <= (widest channel) * sum |B u|, with B u of the returned velocity.
+    Bu = oracle.Oracle(m, force).apply(oracle.OP_B, u)
+    bound = max(ws) * np.abs(Bu).sum()
+    say(f"    sum u_y = {u[1].sum():.3e}, bound {bound:.3e}, ||B u|| = {rep['div_norm']:.3e}")
+    assert abs(u[1].sum()) <= bound + 1e-14 * np.abs(u[0]).sum()
+    assert abs(rep["mean_u"][1] - u[1].sum() / N ** 3) <= 1e-15 * np.abs(u[0]).sum() / N ** 3
+    assert rep["div_norm"] <= 1.01e-8 * rep["r0_norm"]
 
 
 def test_mixed_matches_fp64_gpu(P):

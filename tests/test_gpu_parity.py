@@ -224,6 +224,54 @@ def test_slit_closed_form_gpu(P, axis, fdir):
     assert rep["k_vox"] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-11)
 
 
+@pytest.mark.parametrize("W", [4, 16, 32])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_slit_stack_128_along_channels(P, W, precision):
+    """128^3 slit stack, 2-voxel walls, force along the channels, multigrid on both
+    inner solves: g = B A^-1 f is zero in exact arithmetic; the computed one sits at
+    the inner solve's error, below the floor, so no outer step is taken and the
+    flux is the plane Poiseuille closed form W (W^2 + 2)/12 per channel."""
+    N = 128
+    say(f"[slit stack 128] W={W} along the channels precision={precision}")
+    m = slits(N, W, axis=1)
+    ws = channel_widths(N, W)
+    for pc in (P.STOKES_SIMPLE, P.STOKES_UZAWA):
+        with P.Stokes(m, (1.0, 0.0, 0.0), precision=precision) as s:
+            info = s.info()
+            assert info["mg_levels_S"] >= 3 and info["mg_levels_A"] >= 3
+            rep = s.solve(pc, 1e-8)
+        say(f"    pc={pc} outer={rep['outer_iters']} r0={rep['r0_norm']:.3e} flags={rep['flags']} "
+            f"k_vox={rep['k_vox']:.15e}")
+        assert rep["status"] == 0
+        assert rep["outer_iters"] == 0 and rep["flags"] & P.STOKES_FLAG_ZERO_RHS
+        assert rep["k_vox"] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-9)
+        assert abs(rep["mean_u"][1]) == 0.0 and abs(rep["mean_u"][2]) == 0.0
+
+
+@pytest.mark.parametrize("W", [4, 16])
+def test_slit_stack_128_oblique(P, W):
+    """128^3 slit stack with the force (1, 0.5, 0): the exact solution has u_y = 0,
+    a pressure rising by f_y per voxel across each channel, and the channel flux
+    of the closed form; multigrid on both inner solves."""
+    N = 128
+    say(f"[slit stack 128] W={W} oblique force")
+    m = slits(N, W, axis=1)
+    ws = channel_widths(N, W)
+    with P.Stokes(m, (1.0, 0.5, 0.0)) as s:
+        rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+        p, u = s.fields()
+    say(f"    outer={rep['outer_iters']} innerA={rep['inner_A_iters']} innerS={rep['inner_S_iters']} "
+        f"mean_u={rep['mean_u']}")
+    assert rep["status"] == 0 and rep["outer_iters"] > 0
+    assert rep["mean_u"][0] == pytest.approx(sum(w * (w * w + 2) / 12.0 for w in ws) / N, rel=1e-8)
+    # pressure steps of f_y across every active y-face (B^T p = f_y where u_y = 0)
+    fl = m.astype(bool)
+    act_y = fl & np.roll(fl, 1, axis=1)
+    dp = (p - np.roll(p, 1, axis=1))[act_y]
+    assert np.abs(dp - 0.5).max() < 1e-6
+    assert np.abs(u[1]).max() < 1e-6 * np.abs(u[0]).max()
+
+
 def test_no_flow_geometry(P):
     """Force normal to all walls: no conducting fluid, k = 0 exactly, no device solve."""
     m = slits(16, 4, axis=0)

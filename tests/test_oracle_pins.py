@@ -328,6 +328,56 @@ def test_energy_identity_and_divergence(oracle_mod):
 
 
 # --------------------------------------------------------------------------
+# Zero right-hand side: ||g||^2 <= f . A^{-1} f (dense algebra), and the floor
+# zero_rhs_factor * eps_A * sqrt(f . u0) separates channels along the force
+# (exact g = 0) from geometries with a real pressure, however small
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,seed,phi", [(5, 1, 0.7), (6, 2, 0.8), (7, 3, 0.6)])
+def test_rhs_energy_bound(oracle_mod, N, seed, phi):
+    """S = B A^-1 B^T has no eigenvalue above 1, so ||g||^2 <= g^T S^+ g <= f^T A^-1 f;
+    checked with dense matrices and a dense solve, independently of the oracle's CG."""
+    o = oracle.Oracle(random_mask(N, seed, phi), (1, 0.3, 0))
+    A, B, BT = dense_ops(o)
+    fp, _ = o.unknowns()
+    f = np.array([o.force[pos // N ** 3] for pos in fp])
+    u0 = np.linalg.solve(A, f)
+    g = B @ u0
+    _, comp = o.masks()
+    _, cp = o.unknowns()
+    lab = comp.ravel()[cp]
+    for q in range(o.ncomp_kept):           # the projected g (zero mean per component)
+        g[lab == q] -= g[lab == q].mean()
+    S = B @ np.linalg.solve(A, BT)
+    gSg = g @ np.linalg.lstsq(S, g, rcond=1e-12)[0]
+    assert g @ g <= gSg * (1 + 1e-10) + 1e-14
+    assert gSg <= (f @ u0) * (1 + 1e-10)
+    r = o.solve(oracle.SIMPLE, **TIGHT)
+    assert r["r0"] == pytest.approx(np.linalg.norm(g), rel=1e-9)
+    assert r["f_dot_u0"] == pytest.approx(f @ u0, rel=1e-10)
+    assert not r["zero_rhs"] and r["r0"] > 1e-4 * np.sqrt(r["f_dot_u0"])
+
+
+def test_zero_rhs_floor_separates_channels_from_bumps(oracle_mod):
+    """Slits with the force along the channels have g = 0 exactly; one solid voxel
+    in a channel gives a small real g that stays far above the floor."""
+    N = 16
+    m = slits(N, [6, 4], axis=1)
+    r = oracle.Oracle(m, (1, 0, 0)).solve(oracle.SIMPLE, **TIGHT)
+    assert r["zero_rhs"] and r["outer_iters"] == 0 and r["r0"] == 0.0
+    ws = channel_widths(N, [6, 4])
+    assert r["k_vox"] == pytest.approx(slit_kvox(N, ws), rel=1e-11)
+    mb = m.copy()
+    fl = np.argwhere(mb == 1)
+    k, j, i = fl[len(fl) // 2]
+    mb[k, j, i] = 0
+    rb = oracle.Oracle(mb, (1, 0, 0)).solve(oracle.SIMPLE, **TIGHT)
+    assert not rb["zero_rhs"] and rb["outer_iters"] > 0
+    ratio = rb["r0"] / np.sqrt(rb["f_dot_u0"])
+    assert 1e3 * 1e-13 * 1e4 < ratio < 1.0
+    assert rb["k_vox"] < r["k_vox"]
+
+
+# --------------------------------------------------------------------------
 # P13: Lanczos Ritz values from the CG coefficients bracket the spectrum
 # --------------------------------------------------------------------------
 def test_lanczos_extreme_eigenvalues(oracle_mod):
