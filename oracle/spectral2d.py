@@ -168,7 +168,8 @@ def operators_2d_sparse(m: np.ndarray):
     return A, B
 
 
-def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10000, coeffs: list = None):
+def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10000, coeffs: list = None,
+                 diag_offset: float = 0.0):
     """Outer PCG on S p = g (Algorithm 1 with the standard signs) for a unit
     force along x, inner solves with A and with the SIMPLE matrix done by sparse
     LU (so the inner solves are exact to rounding, the paper's tight inner
@@ -176,7 +177,11 @@ def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10
     as in the paper's 2D runs.  Returns (iterations, permeability per pixel of
     the box, ||r|| / ||r0|| at exit); the fluid must form one component.  If
     `coeffs` is a list, the (alpha, beta) pairs of the iterations are appended
-    to it (for the Lanczos estimate of the spectrum seen by g)."""
+    to it (for the Lanczos estimate of the spectrum seen by g).  diag_offset
+    adds a constant to diag(A) inside the SIMPLE matrix only: 2 gives the SIMPLE
+    matrix that a 3D box made of copies of this image along z sees on fields
+    that do not vary along z (its A has two more active neighbours per face,
+    so diag(A) = 6 + t instead of 4 + t, while A itself acts the same)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as sla
     A, B = operators_2d_sparse(m)
@@ -188,7 +193,7 @@ def schur_pcg_2d(m: np.ndarray, precond: str, tol: float = 1e-3, maxit: int = 10
     luA = sla.splu(A.tocsc())
     nc = B.shape[0]
     if precond == "simple":
-        Sh = (B @ sp.diags(1.0 / A.diagonal()) @ B.T).tolil()
+        Sh = (B @ sp.diags(1.0 / (A.diagonal() + diag_offset)) @ B.T).tolil()
         Sh[0, :] = 0.0
         Sh[:, 0] = 0.0
         Sh[0, 0] = 1.0                                      # ground one cell: the system is consistent on range(B)

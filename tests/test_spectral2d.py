@@ -161,3 +161,39 @@ def test_paper_2d_outer_counts_in_band(idx):
     k_u = schur_pcg_2d(m, "uzawa")[0]
     assert abs(k_s - (t["simple_iterations"][idx] - 1)) <= 3
     assert abs(k_u - t["uzawa_iterations"][idx]) <= 0.2 * t["uzawa_iterations"][idx]
+
+
+@pytest.mark.parametrize("Nq,n_c,n_avg,seed", [(3, 8, 4, 0), (2, 12, 6, 1), (4, 6, 4, 2)])
+def test_3d_oracle_on_extruded_squares_matches_2d(oracle_mod, Nq, n_c, n_avg, seed):
+    """Ties the 3D oracle's outer loop and its iteration count to the 2D code that
+    reproduces the paper's 2D table: a box made of copies of a 2D square array along
+    z carries exactly the 2D flow (the CG iterates stay constant along z), so at the
+    paper's 2D stopping rule (1e-3 on ||r||/||r0||) the 3D oracle must take the same
+    outer iterations with the same coefficients and give the 2D flux per pixel.
+    Uzawa: identical problems.  SIMPLE: the 3D A has two more active neighbours per
+    face (along z), so its SIMPLE matrix uses diag(A) = 6 + t; the 2D reference is run
+    with that diagonal (diag_offset 2), and without it the trajectories differ."""
+    import oracle
+    from oracle.spectral2d import schur_pcg_2d
+    m2 = squares_2d(Nq, n_c, n_avg, 2, seed)
+    n = m2.shape[0]
+    m3 = np.ascontiguousarray(np.broadcast_to(m2[None, :, :], (n, n, n)))
+    o = oracle.Oracle(m3, (1.0, 0.0, 0.0))
+    for pc, pid in (("uzawa", oracle.UZAWA), ("simple", oracle.SIMPLE)):
+        co = []
+        k2, perm2, res2 = schur_pcg_2d(m2, pc, tol=1e-3, coeffs=co, diag_offset=2.0 if pc == "simple" else 0.0)
+        r = o.solve(pid, tol=1e-3, eps_A=1e-13, eps_S=1e-13, true_u=True)
+        assert r["outer_iters"] == k2
+        co = np.array(co)
+        np.testing.assert_allclose(r["hist"][:, 5], co[:, 0], rtol=1e-8)
+        np.testing.assert_allclose(r["hist"][:-1, 6], co[:-1, 1], rtol=1e-8)
+        assert r["rel_res"] == pytest.approx(res2, rel=1e-4)
+        # flux of u = A^-1 (f - B^T p): u is a small difference of two large terms
+        # in narrow channels, so coefficients equal to 1e-8 leave k equal to ~1e-7
+        assert r["k_hat_true"] * n * n == pytest.approx(perm2, rel=1e-6)
+        assert r["k_vox"] == pytest.approx(perm2, rel=1e-6)
+        assert np.abs(r["u"][2]).max() < 1e-12 * np.abs(r["u"][0]).max()
+    # the plain 2D SIMPLE matrix (diag 4 + t) is a different preconditioner
+    co2 = []
+    schur_pcg_2d(m2, "simple", tol=1e-3, coeffs=co2)
+    assert abs(co2[0][0] - r["hist"][0, 5]) > 1e-3 * abs(co2[0][0])
