@@ -252,6 +252,34 @@ stokes_status stokes_apply(stokes_ctx *ctx, int op, const double *in, double *ou
  * returns without waiting for it. */
 stokes_status stokes_apply_device(stokes_ctx *ctx, int op, const double *in, double *out);
 
+/*
+ * stokes_apply_device_noalloc -- for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  As stokes_apply_device, with the same kernels and the
+ * same results bitwise, but the masked copy of the input and the partial sums
+ * of the projection live in a fixed 32 MiB device array of the library (one
+ * copy per GPU, held until the process ends; its address is resolved when a
+ * context is set up on that GPU) instead of the context's work vectors, and
+ * the result goes straight to `out`.  The call allocates nothing and issues
+ * only device-to-device copies and kernel launches on the context's stream;
+ * it returns without waiting.
+ *   op       STOKES_OP_A, _B, _BT, _SHAT, _DIAG_A, _DIAG_SHAT or _PROJECT;
+ *            the inner-solve and V-cycle operators (STOKES_OP_S, _MG_SHAT,
+ *            _MG_A) need the context's work vectors: STOKES_E_ARG.
+ *   in, out  device pointers, sizes as for stokes_apply (in is ignored by the
+ *            DIAG operators; in == out is allowed for STOKES_OP_PROJECT only,
+ *            otherwise the two must not overlap).
+ * Limit: the input copy (3 N^3 doubles for A and B, N^3 for B^T and the
+ * SIMPLE matrix; none for PROJECT and the DIAG operators) plus the partial
+ * sums (at most 4096 doubles, or 257 K for K > 1 components) must fit in
+ * 32 MiB, i.e. N <= 111 for A and B, N <= 161 for B^T and SHAT; beyond it
+ * the call returns STOKES_E_LIMIT and does no device work.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU (several streams or threads)
+ * race, and the caller must order them (e.g. one stream).
+ */
+stokes_status stokes_apply_device_noalloc(stokes_ctx *ctx, int op, const double *in, double *out);
+
 /* info[0..11]: N, fluid voxels (as given), fluid voxels kept, surface voxels,
  * components (as given), components kept, active x/y/z faces (3 values),
  * device bytes held, coarse levels of the multigrid hierarchy for the SIMPLE

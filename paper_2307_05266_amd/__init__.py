@@ -17,6 +17,7 @@ from .stokes import (  # noqa: F401
     load,
     stokes_apply,
     stokes_apply_device,
+    stokes_apply_device_noalloc,
     stokes_destroy,
     stokes_get_fields,
     stokes_history,
@@ -43,4 +44,12 @@ from .stokes import (  # noqa: F401
     STOKES_FLAG_NO_FLOW,
     STOKES_FLAG_ZERO_RHS,
     STOKES_FLAG_INNER_MAXIT,
+    STOKES_OK,
+    STOKES_NOT_CONVERGED,
+    STOKES_E_ARG,
+    STOKES_E_NOMEM,
+    STOKES_E_DEVICE,
+    STOKES_E_BREAKDOWN,
+    STOKES_E_STATE,
+    STOKES_E_LIMIT,
 )

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -82,6 +83,8 @@ struct stokes_ctx {
     double force[3] = {0, 0, 0};
     unsigned setup_flags = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                // the device current at setup
+    double* noalloc_scratch = nullptr;  // this device's copy of `scratch` (stokes_apply_device_noalloc)
 
     // geometry summary
     int64_t nfluid_in = 0, nfluid = 0, nsurf = 0;
@@ -803,27 +806,35 @@ stokes_status solve_A64(stokes_ctx* c, const double* b, double eps, int* iters, 
 }
 
 // ---- outer-loop helpers ---------------------------------------------------------
-stokes_status project(stokes_ctx* c, double* x) {
+// Remove each kept component's mean from the cell vector x.  part and mean are
+// the partial sums (kMaxBlocks values for one component, kCompBlocks * K for
+// several) and the K means; every entry read is written first in the call.
+stokes_status project_with(stokes_ctx* c, double* x, double* part, double* mean) {
     const int K = c->ncomp_kept;
     if (K == 0) return STOKES_OK;
     if (K == 1 && !c->label) {
-        hipLaunchKernelGGL(k_sum1, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, (const double*)x, c->proj_part);
+        hipLaunchKernelGGL(k_sum1, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, (const double*)x, part);
         hipLaunchKernelGGL(k_sub_mean1, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, x, c->bits, c->wpr,
-                           (const double*)c->proj_part, 1.0 / (double)c->nfluid);
+                           (const double*)part, 1.0 / (double)c->nfluid);
         HIP_TRY(hipGetLastError());
         return STOKES_OK;
     }
     const int64_t chunk = ((c->n3 + kCompBlocks - 1) / kCompBlocks + 255) / 256 * 256;
     const int nb = (int)((c->n3 + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_comp_sum, dim3(nb), dim3(kBlock), (size_t)kWaves * K * sizeof(double), c->stream, x,
-                       c->label, c->bits, c->N, c->wpr, c->n3, K, chunk, c->comp_part);
-    hipLaunchKernelGGL(k_comp_mean, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, c->comp_part, nb, K,
-                       c->comp_count, c->comp_mean);
+                       c->label, c->bits, c->N, c->wpr, c->n3, K, chunk, part);
+    hipLaunchKernelGGL(k_comp_mean, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, part, nb, K,
+                       c->comp_count, mean);
     const int subblocks = (int)std::min<int64_t>(4096, (c->n3 + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_comp_sub, dim3(subblocks), dim3(kBlock), 0, c->stream, x, c->label, c->bits, c->N, c->wpr,
-                       c->n3, c->comp_mean);
+                       c->n3, mean);
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
+}
+
+stokes_status project(stokes_ctx* c, double* x) {
+    const bool one = c->ncomp_kept == 1 && !c->label;
+    return project_with(c, x, one ? c->proj_part : c->comp_part, c->comp_mean);
 }
 
 // per-block partials [3 * nblk] to the host, added there in block order
@@ -904,6 +915,39 @@ void lanczos_extremes(const std::vector<double>& alpha, const std::vector<double
     *hi = kth((int)k - 1);
 }
 
+}  // namespace
+
+// ---- scratch of the no-allocation entry point ------------------------------------
+// stokes_apply_device_noalloc keeps the masked copy of its input and the
+// partial sums of the projection in this fixed array instead of the context's
+// work vectors.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code the name stands for a host-side shadow, not a
+// device address: host code only ever uses the address that
+// hipGetSymbolAddress returns with the device current (scratch_address).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int64_t kNoAllocScratchWords = (int64_t)(kNoAllocScratchBytes / sizeof(double));
+static __device__ __align__(256) double scratch[kNoAllocScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mutex;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// resolved once per device and kept.
+stokes_status scratch_address(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return STOKES_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return STOKES_E_DEVICE;
+        g_scratch_addr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[device];
+    return STOKES_OK;
+}
 }  // namespace
 
 // ============================================================================
@@ -1064,6 +1108,10 @@ static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, 
     } catch (const std::bad_alloc&) {
         st = STOKES_E_NOMEM;
     }
+    // the device this context runs on, and that device's copy of the
+    // no-allocation scratch (resolved here, at set-up, with the device current)
+    if (st >= 0 && hipGetDevice(&c->device) != hipSuccess) st = STOKES_E_DEVICE;
+    if (st >= 0) st = scratch_address(c->device, &c->noalloc_scratch);
     if (st < 0) {
         release(c);
         delete c;
@@ -1679,6 +1727,61 @@ stokes_status stokes_apply(stokes_ctx* c, int op, const double* in, double* out)
 stokes_status stokes_apply_device(stokes_ctx* c, int op, const double* in, double* out) {
     if (!c || !out || op < 0 || op > STOKES_OP_MG_A) return STOKES_E_ARG;
     return apply_impl(c, op, in, out, hipMemcpyDeviceToDevice, hipMemcpyDeviceToDevice);
+}
+
+// The variant of stokes_apply_device that allocates nothing: the same kernels,
+// with the masked input copy and the projection's partial sums in `scratch`
+// (this device's copy, resolved at set-up) and the result written straight to
+// `out`.  Layout in scratch (doubles): [partials, rounded up to 256 bytes]
+// [input copy].  Only device copies and kernel launches on the context's
+// stream: no allocation, no memset, no synchronisation.
+stokes_status stokes_apply_device_noalloc(stokes_ctx* c, int op, const double* in, double* out) {
+    if (!c || !out) return STOKES_E_ARG;
+    if (op != STOKES_OP_A && op != STOKES_OP_B && op != STOKES_OP_BT && op != STOKES_OP_SHAT &&
+        op != STOKES_OP_DIAG_A && op != STOKES_OP_DIAG_SHAT && op != STOKES_OP_PROJECT)
+        return STOKES_E_ARG;
+    const bool no_in = op == STOKES_OP_DIAG_A || op == STOKES_OP_DIAG_SHAT;
+    const bool face_in = op == STOKES_OP_A || op == STOKES_OP_B;
+    if (!no_in && !in) return STOKES_E_ARG;
+    double* base = c->noalloc_scratch;
+    if (!base) return STOKES_E_DEVICE;
+    const Sweep& s = c->sw;
+    const int64_t n3 = c->n3;
+    const int K = c->ncomp_kept;
+    const bool one = K == 1 && !c->label;
+    int64_t part_words = 0, mean_off = 0;
+    if (op == STOKES_OP_PROJECT && K > 0) {
+        part_words = one ? (int64_t)kMaxBlocks : (int64_t)kCompBlocks * K;
+        mean_off = part_words;
+        part_words += one ? 0 : K;
+    }
+    part_words = (part_words + 31) / 32 * 32;
+    const int64_t in_words = (no_in || op == STOKES_OP_PROJECT) ? 0 : (face_in ? 3 : 1) * n3;
+    if (part_words + in_words > kNoAllocScratchWords) return STOKES_E_LIMIT;
+    if (op == STOKES_OP_PROJECT) {
+        // in place on out: copy, mask, remove the component means
+        if (out != in)
+            HIP_TRY(hipMemcpyAsync(out, in, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(k_mask_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->bits, c->wpr, out);
+        HIP_TRY(hipGetLastError());
+        return project_with(c, out, base, base + mean_off);
+    }
+    double* src = base + part_words;
+    if (!no_in) {
+        HIP_TRY(hipMemcpyAsync(src, in, (size_t)in_words * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        if (face_in) hipLaunchKernelGGL(k_mask_faces, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src);
+        else hipLaunchKernelGGL(k_mask_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->bits, c->wpr, src);
+    }
+    switch (op) {
+    case STOKES_OP_A: hipLaunchKernelGGL(k_apply_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, out); break;
+    case STOKES_OP_B: hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, src, out); break;
+    case STOKES_OP_BT: hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, out); break;
+    case STOKES_OP_SHAT: hipLaunchKernelGGL(k_apply_Shat, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, src, out); break;
+    case STOKES_OP_DIAG_A: hipLaunchKernelGGL(k_diag_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, out); break;
+    default: hipLaunchKernelGGL(k_diag_Shat, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, out); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return STOKES_OK;
 }
 
 stokes_status stokes_info(stokes_ctx* c, int64_t info[12]) {

@@ -32,7 +32,7 @@ EXPORTED = [
     "stokes_permeability", "stokes_get_report", "stokes_history", "stokes_get_fields",
     "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
     "stokes_destroy", "stokes_status_str", "stokes_preprocess", "stokes_setup_on_stream",
-    "stokes_estimate_bytes",
+    "stokes_estimate_bytes", "stokes_apply_device_noalloc",
 ]
 EXPORTED_SERVER = [
     "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
@@ -105,6 +105,7 @@ def load():
         "stokes_get_fields": ([vp, vp, vp], ip),
         "stokes_apply": ([vp, ip, vp, vp], ip),
         "stokes_apply_device": ([vp, ip, vp, vp], ip),
+        "stokes_apply_device_noalloc": ([vp, ip, vp, vp], ip),
         "stokes_info": ([vp, i64p], ip),
         "stokes_kernel_timing": ([vp, ip, dp, i64p, dp], ip),
         "stokes_destroy": ([vp], None),
@@ -238,6 +239,19 @@ def stokes_apply_device(ctx, op, x, out):
                   "stokes_apply_device")
 
 
+def stokes_apply_device_noalloc(ctx, op, x, out, ok=(STOKES_OK,)):
+    """As stokes_apply_device, through the entry point that allocates nothing
+    (its scratch is the library's fixed device array).  Returns the status;
+    statuses outside `ok` raise StokesError."""
+    for t in (x, out):
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError("stokes_apply_device_noalloc needs contiguous float64 GPU tensors")
+    xp = x.data_ptr() if x is not None else None
+    return _check(load().stokes_apply_device_noalloc(ctx, int(op), ctypes.c_void_p(xp),
+                                                     ctypes.c_void_p(out.data_ptr())),
+                  "stokes_apply_device_noalloc", ok)
+
+
 def stokes_info(ctx):
     info = (ctypes.c_int64 * 12)()
     _check(load().stokes_info(ctx, info), "stokes_info")
@@ -305,6 +319,9 @@ class Stokes:
 
     def apply_device(self, op, x, out):
         return stokes_apply_device(self._ctx, op, x, out)
+
+    def apply_device_noalloc(self, op, x, out, ok=(STOKES_OK,)):
+        return stokes_apply_device_noalloc(self._ctx, op, x, out, ok)
 
     def info(self):
         return stokes_info(self._ctx)
