@@ -28,7 +28,8 @@
  * pressure of each remaining component is fixed to zero mean (Sec. 2.2).
  *
  * Memory and streams: a context owns all of its device memory from setup to
- * destroy.  All device work of a context runs on one HIP stream (the
+ * destroy (from hipMalloc, stream-ordered allocation, or the caller's
+ * allocator: stokes_setup_with_allocator).  All device work of a context runs on one HIP stream (the
  * default stream unless stokes_set_stream is called).  A context must not be
  * used from two threads at once; distinct contexts are independent.
  *
@@ -38,6 +39,7 @@
 #ifndef STOKES_H
 #define STOKES_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -136,6 +138,36 @@ stokes_status stokes_setup_ex(stokes_ctx **ctx, const uint8_t *mask, int N, cons
  */
 stokes_status stokes_setup_on_stream(stokes_ctx **ctx, const uint8_t *mask, int N, const double force[3],
                                      unsigned flags, void *stream);
+
+/*
+ * Device memory from the caller.  alloc returns `bytes` of device memory
+ * usable in the order of `stream` (the context's stream, a hipStream_t; NULL =
+ * the default stream), or NULL when it cannot; free takes back a block that
+ * alloc returned, with the same size and stream.  user is passed through.
+ * Both may be called from stokes_setup_with_allocator, stokes_set_option
+ * ("precision" allocates the FP32 vectors on first use) and stokes_destroy,
+ * always from the thread making that call.
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+    void *user;
+} stokes_allocator;
+
+/*
+ * stokes_setup_with_allocator -- as stokes_setup_ex, with every device buffer
+ * of the context taken from the caller's allocator (e.g. a framework's caching
+ * allocator, so that the solver shares one memory pool with the caller) and
+ * all of the context's device work on `stream` (NULL = the default stream).
+ * The allocator struct is copied; its functions must stay callable until
+ * stokes_destroy returns, which waits for the stream before freeing.  Every
+ * buffer is cleared on the stream after it is allocated, so reused memory is
+ * fine.  STOKES_E_ARG when alloc is NULL or lacks either function;
+ * STOKES_E_NOMEM when the allocator returns NULL (everything taken so far is
+ * freed again).
+ */
+stokes_status stokes_setup_with_allocator(stokes_ctx **ctx, const uint8_t *mask, int N, const double force[3],
+                                          unsigned flags, void *stream, const stokes_allocator *alloc);
 
 /*
  * stokes_estimate_bytes -- upper bound of the device bytes a context for an

@@ -145,9 +145,10 @@ struct stokes_ctx {
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
-    std::vector<void*> allocations;
+    std::vector<std::pair<void*, size_t>> allocations;
     int64_t device_bytes = 0;
     bool async_alloc = false;      // allocations ordered on `stream` (stokes_setup_on_stream)
+    stokes_allocator ext_alloc{};  // caller's allocator (stokes_setup_with_allocator), else all NULL
     int progress = 0;              // > 0: report every n-th outer iteration on stderr
     std::chrono::steady_clock::time_point t_solve0;
     CgState* host_state = nullptr; // pinned
@@ -229,16 +230,26 @@ Sweep make_sweep32(int N, int target_blocks) {
 const Sweep& inner_sweep(const stokes_ctx* c, double) { return c->sw; }
 const Sweep& inner_sweep(const stokes_ctx* c, float) { return c->sw32; }
 
+// Every device buffer of a context comes from here: the caller's allocator
+// when one was given, else stream-ordered allocation for contexts set up on a
+// stream (concurrent contexts never wait on each other's allocations), else
+// hipMalloc.  Each buffer is cleared on the context's stream, so no kernel
+// depends on what the memory held before (a caching allocator hands back
+// used memory).
 template <class T>
 stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
     void* m = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    // contexts set up on a stream allocate and free in that stream's order, so
-    // concurrent contexts never wait on each other's allocations
-    const hipError_t e = c->async_alloc ? hipMallocAsync(&m, bytes, c->stream) : hipMalloc(&m, bytes);
-    if (e != hipSuccess) return STOKES_E_NOMEM;
-    c->allocations.push_back(m);
+    if (c->ext_alloc.alloc) {
+        m = c->ext_alloc.alloc(bytes, (void*)c->stream, c->ext_alloc.user);
+        if (!m) return STOKES_E_NOMEM;
+    } else {
+        const hipError_t e = c->async_alloc ? hipMallocAsync(&m, bytes, c->stream) : hipMalloc(&m, bytes);
+        if (e != hipSuccess) return STOKES_E_NOMEM;
+    }
+    c->allocations.push_back({m, bytes});
     c->device_bytes += (int64_t)bytes;
+    HIP_TRY(hipMemsetAsync(m, 0, bytes, c->stream));
     *ptr = static_cast<T*>(m);
     return STOKES_OK;
 }
@@ -248,8 +259,15 @@ void release(stokes_ctx* c) {
     c->graphs.clear();
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
-    for (void* m : c->allocations) (void)(c->async_alloc ? hipFreeAsync(m, c->stream) : hipFree(m));
-    if (c->async_alloc && c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->ext_alloc.alloc) {
+        // the caller's allocator may hand the memory to other work at once
+        (void)(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+        for (auto& a : c->allocations) c->ext_alloc.free(a.first, a.second, (void*)c->stream, c->ext_alloc.user);
+    } else {
+        for (auto& a : c->allocations)
+            (void)(c->async_alloc ? hipFreeAsync(a.first, c->stream) : hipFree(a.first));
+        if (c->async_alloc && c->stream) (void)hipStreamSynchronize(c->stream);
+    }
     c->allocations.clear();
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
@@ -1089,7 +1107,7 @@ stokes_status stokes_preprocess(const uint8_t* mask, int N, const double force[3
 }
 
 static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
-                                  unsigned flags, hipStream_t stream) {
+                                  unsigned flags, hipStream_t stream, const stokes_allocator* alloc = nullptr) {
     if (!out) return STOKES_E_ARG;
     ST_TRY(check_inputs(mask, N, force, flags));
     const int64_t n3 = (int64_t)N * N * N;
@@ -1101,7 +1119,8 @@ static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, 
     for (int a = 0; a < 3; ++a) c->force[a] = force[a];
     c->setup_flags = flags;
     c->stream = stream;
-    c->async_alloc = stream != nullptr;
+    if (alloc) c->ext_alloc = *alloc;
+    else c->async_alloc = stream != nullptr;
     stokes_status st;
     try {
         st = setup_impl(c, mask);
@@ -1133,6 +1152,12 @@ stokes_status stokes_setup_on_stream(stokes_ctx** out, const uint8_t* mask, int 
                                      unsigned flags, void* stream) {
     if (!stream) return STOKES_E_ARG;
     return setup_common(out, mask, N, force, flags, (hipStream_t)stream);
+}
+
+stokes_status stokes_setup_with_allocator(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
+                                          unsigned flags, void* stream, const stokes_allocator* alloc) {
+    if (!alloc || !alloc->alloc || !alloc->free) return STOKES_E_ARG;
+    return setup_common(out, mask, N, force, flags, (hipStream_t)stream, alloc);
 }
 
 // Mirrors the allocations of setup_impl, build_mg, ensure_mixed_buffers and

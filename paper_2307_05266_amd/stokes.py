@@ -32,7 +32,7 @@ EXPORTED = [
     "stokes_permeability", "stokes_get_report", "stokes_history", "stokes_get_fields",
     "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
     "stokes_destroy", "stokes_status_str", "stokes_preprocess", "stokes_setup_on_stream",
-    "stokes_estimate_bytes", "stokes_apply_device_noalloc",
+    "stokes_estimate_bytes", "stokes_apply_device_noalloc", "stokes_setup_with_allocator",
 ]
 EXPORTED_SERVER = [
     "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
@@ -71,6 +71,48 @@ class StokesRequestResult(ctypes.Structure):
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class StokesAllocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TorchDeviceMemory:
+    """Device memory of a context from PyTorch's caching allocator, on the torch
+    stream the context runs on.  Holds the ctypes callbacks (they must outlive
+    the context) and the blocks it handed out."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.device = stream.device
+        self.live = {}
+
+        def alloc(nbytes, _stream, _user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:   # out of memory: the library reports STOKES_E_NOMEM
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def free(ptr, _nbytes, _stream, _user):
+            if self.live.pop(ptr, None) is not None:
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:   # interpreter shutdown: torch is already gone
+                    pass
+
+        self._alloc = _ALLOC_FN(alloc)
+        self._free = _FREE_FN(free)
+        self.struct = StokesAllocator(self._alloc, self._free, None)
+
+    @property
+    def bytes_held(self):
+        return sum(self.live.values())
 
 
 class StokesError(RuntimeError):
@@ -112,6 +154,8 @@ def load():
         "stokes_status_str": ([ip], ctypes.c_char_p),
         "stokes_preprocess": ([vp, ip, dp, ctypes.c_uint, i64p, vp, vp], ip),
         "stokes_setup_on_stream": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint, vp], ip),
+        "stokes_setup_with_allocator": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint, vp,
+                                         ctypes.POINTER(StokesAllocator)], ip),
         "stokes_estimate_bytes": ([ip, ctypes.c_uint, ip, i64p], ip),
         "stokes_server_create": ([ctypes.POINTER(vp), ip, ctypes.c_int64], ip),
         "stokes_server_submit": ([vp, vp, ip, dp, ip, ctypes.c_double, ip, i64p], ip),
@@ -149,6 +193,21 @@ def stokes_setup(mask, N, force, flags=0):
     st = lib.stokes_setup_ex(ctypes.byref(h), m.ctypes.data, int(N),
                              f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_uint(flags))
     _check(st, "stokes_setup")
+    return h
+
+
+def stokes_setup_with_allocator(mask, N, force, flags, stream, allocator):
+    """stream: a hipStream_t as an int (0 = default); allocator: a StokesAllocator."""
+    lib = load()
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    if m.size != N ** 3:
+        raise ValueError("mask must hold N^3 bytes")
+    f = np.ascontiguousarray(force, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = lib.stokes_setup_with_allocator(ctypes.byref(h), m.ctypes.data, int(N),
+                                         f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_uint(flags),
+                                         ctypes.c_void_p(stream), ctypes.byref(allocator))
+    _check(st, "stokes_setup_with_allocator")
     return h
 
 
@@ -285,14 +344,31 @@ def stokes_destroy(ctx):
 class Stokes:
     """One geometry on the GPU.  mask: uint8 (N, N, N) indexed [k][j][i], 1 = fluid."""
 
-    def __init__(self, mask, force=(1.0, 0.0, 0.0), keep_all=False, stream=None, **options):
+    def __init__(self, mask, force=(1.0, 0.0, 0.0), keep_all=False, stream=None, torch_memory=True, **options):
+        """stream: a torch.cuda.Stream or a raw hipStream_t (int); default the
+        current torch stream.  torch_memory: the context's device memory comes
+        from torch's caching allocator on that stream (default); False: the
+        library allocates it with hipMalloc."""
         mask = np.asarray(mask)
         self.N = int(mask.shape[0])
-        self._ctx = stokes_setup(mask, self.N, force, STOKES_KEEP_ALL_COMPONENTS if keep_all else 0)
-        if stream is None and torch.cuda.is_available():
-            stream = torch.cuda.current_stream().cuda_stream
-        if stream is not None:
-            stokes_set_stream(self._ctx, stream)
+        flags = STOKES_KEEP_ALL_COMPONENTS if keep_all else 0
+        self._mem = None
+        if torch.cuda.is_available():
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            elif isinstance(stream, int):
+                stream = torch.cuda.ExternalStream(stream)
+            if torch_memory:
+                self._mem = TorchDeviceMemory(stream)
+                self._ctx = stokes_setup_with_allocator(mask, self.N, force, flags, stream.cuda_stream,
+                                                        self._mem.struct)
+            else:
+                self._ctx = stokes_setup(mask, self.N, force, flags)
+                stokes_set_stream(self._ctx, stream.cuda_stream)
+        else:
+            self._ctx = stokes_setup(mask, self.N, force, flags)
+            if stream is not None:
+                stokes_set_stream(self._ctx, stream if isinstance(stream, int) else stream.cuda_stream)
         for k, v in options.items():
             stokes_set_option(self._ctx, k, v)
 
