@@ -1,18 +1,22 @@
 """Benchmark: permeability solves per second on one MI355X.
 
-Workload: FP64 solve on a 128^3 periodic box of overlapping solid spheres of
-radius 6 voxels (porosity 0.5, seed 0), unit body force along x, outer CG on
-the pressure Schur complement with the SIMPLE preconditioner to a relative
-residual of 1e-8, inner tolerances 1e-12.  One step is one full solve from
-p = 0 on a context whose geometry is resident in HBM (setup, which reads a
-host mask, runs once before timing and is reported separately), followed by
-the permeability read-back.
+Workload (default): FP64 solve on a 256^3 periodic box of overlapping solid
+spheres of radius 3 voxels packed to porosity 0.2 (seed 0; high
+surface-to-volume ratio), unit body force along x, outer CG on the pressure
+Schur complement with the SIMPLE preconditioner to a relative residual of
+1e-8, inner tolerances 1e-12.  One step is one full solve from p = 0 on a
+context whose geometry is resident in HBM (setup, which reads a host mask,
+runs once before timing and is reported separately), followed by the
+permeability read-back.  Beside it: the same solve in mixed precision, one
+mixed-precision solve of the 512^3 Gaussian-random-field geometry, and a short
+seeded stream of mixed-precision requests (box sides 32..128) through the
+request server with its throughput and p50/p99 latency (`--serve-only
+--requests 2000` runs the full serving workload alone).
 
-Beside it, the same run serves a short seeded stream of mixed-precision
-requests (box sides 32..128, spheres or Gaussian-random-field geometries,
-Poisson arrivals at 0.8 of the measured saturated rate) through the request
-server, and reports its throughput and p50/p99 latency.  `--serve-only
---requests 2000` runs the full serving workload alone.
+The CPU baseline times the oracle's own inner iterations on the same
+geometry on the host cores and scales them with the oracle's own Jacobi inner
+iteration counts for this geometry, which `--oracle-counts` measures (a CPU
+run of the oracle's first solves, minutes long) and stores under profiles/.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -131,47 +135,164 @@ def measured_traffic(kernel, N):
     return entry["traffic_bytes"] if entry else None
 
 
-def cpu_baseline(mask, gpu_rep, budget_s=20.0):
-    """Time the oracle on a bounded sample of the same workload and scale it to
-    one solve: one inner A solve (u0 = A^-1 f) and a capped run of inner SIMPLE
-    iterations on the same geometry give the oracle's cost per inner iteration;
-    a solve costs the inner iteration totals that the GPU solve needed."""
-    import numpy as np
+def _sha16(data: bytes) -> str:
+    import hashlib
+    return hashlib.sha256(data).hexdigest()[:16]
 
+
+def oracle_counts_path(workload):
+    return os.path.join(ROOT, "profiles", f"oracle_inner_counts_{workload}.md")
+
+
+def read_json_block(path):
+    """The JSON code block of a committed summary under profiles/."""
+    import re
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        raise ValueError(f"no JSON block in {path}")
+    return json.loads(m.group(1))
+
+
+def oracle_source_hash():
+    return _sha16(open(os.path.join(ROOT, "oracle", "stokes_oracle.c"), "rb").read())
+
+
+def measure_oracle_counts(workload, outer=2):
+    """CPU only: the oracle's own Jacobi-PCG inner iteration counts on a workload
+    (its first inner solves: u0 = A^-1 f and the SIMPLE solve of g, then the
+    first `outer` outer iterations), written to profiles/ for the CPU baseline."""
+    import numpy as np
     import oracle
+    desc, N, gen = WORKLOADS[workload]
+    mask = gen()
+    log(f"[oracle-counts] {desc}: assembling")
+    t0 = time.perf_counter()
     o = oracle.Oracle(mask, (1.0, 0.0, 0.0))
-    N = mask.shape[0]
-    f = np.zeros((3, N, N, N))
-    dA = o.apply(oracle.OP_DIAG_A, None)
-    f[0] = (dA[0] > 0)
+    t_setup = time.perf_counter() - t0
+    log(f"[oracle-counts] assembled in {t_setup:.1f} s: {o.nf} face and {o.nc} cell unknowns; solving "
+        f"with max_outer={outer} on {oracle.threads()} threads")
     t0 = time.perf_counter()
-    _, itA = o.inner_solve(0, f, eps=1e-12, maxit=100000)
-    tA = (time.perf_counter() - t0) / max(itA, 1)
-    rng = np.random.default_rng(0)
-    b = o.apply(oracle.OP_B, rng.standard_normal((3, N, N, N)))
-    nS = max(10, int(min(400, (budget_s - tA * itA) / max(tA, 1e-3) / 2)))
-    t0 = time.perf_counter()
-    _, itS = o.inner_solve(1, b, eps=1e-300, maxit=nS)
-    itS = abs(itS) if itS >= 0 else -itS - 1
-    tS = (time.perf_counter() - t0) / max(itS, 1)
-    est = gpu_rep["inner_A_iters"] * tA + gpu_rep["inner_S_iters"] * tS
-    model = ""
+    r = o.solve(oracle.SIMPLE, tol=1e-8, eps_A=1e-12, eps_S=1e-12, max_outer=outer)
+    dt = time.perf_counter() - t0
+    h = r["hist"]
+    per_outer_A = [int(v) for v in h[:, 3]]
+    per_outer_S = [int(v) for v in h[:, 4]]
+    rec = {
+        "workload": workload, "description": desc, "N": N,
+        "mask_sha256_16": _sha16(np.ascontiguousarray(mask).tobytes()),
+        "oracle_c_sha256_16": oracle_source_hash(),
+        "precond": "simple", "eps_A": 1e-12, "eps_S": 1e-12,
+        "start_A": int(r["inner_A"] - sum(per_outer_A)), "start_S": int(r["inner_S"] - sum(per_outer_S)),
+        "per_outer_A": per_outer_A, "per_outer_S": per_outer_S,
+        "outer_done": int(r["outer_iters"]), "seconds": dt, "threads": oracle.threads(),
+        "command": f"python bench.py --oracle-counts --workload {workload}",
+    }
+    with open(oracle_counts_path(workload), "w") as f:
+        f.write(f"# The oracle's own inner iteration counts on the {desc} workload\n\n"
+                f"Command (repository root, CPU only): `{rec['command']}`\n\n"
+                "The CPU oracle (FP64, CSR over the active unknowns, Jacobi-PCG inner solves to 1e-12) runs its\n"
+                f"SIMPLE solve for {outer} outer iterations on {rec['threads']} threads ({dt:.0f} s).  Its start-up\n"
+                f"solves (u0 = A^-1 f and the SIMPLE solve of g) took {rec['start_A']} A and {rec['start_S']} SIMPLE\n"
+                f"inner iterations; the outer iterations took {per_outer_A} A and {per_outer_S} SIMPLE.  bench.py's\n"
+                "CPU baseline multiplies these counts with the oracle's cost per inner iteration timed on the\n"
+                "GPU box's host cores.\n\n```json\n")
+        json.dump(rec, f, indent=1)
+        f.write("\n```\n")
+    log(f"[oracle-counts] {json.dumps(rec)}")
+
+
+def host_cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown CPU"
+
+
+def cpu_baseline(workload, mask, gpu_rep, iters=30):
+    """The oracle's cost per solve on the same geometry: its cost per inner A and
+    per inner SIMPLE iteration, timed here on the host cores over a bounded run of
+    each, times its own Jacobi inner iteration counts for this geometry (measured
+    by --oracle-counts: the start-up solves, then the mean per outer iteration),
+    times the outer iterations of the solve (the GPU's count; the oracle's agrees
+    within one in every parity case).  None when no stored counts match."""
+    import numpy as np
+    import oracle
+    path = oracle_counts_path(workload)
+    try:
+        rec = read_json_block(path)
+    except (OSError, ValueError):
+        log(f"[bench] no oracle inner counts at {path}; cpu_baseline omitted")
+        return None
+    if rec.get("mask_sha256_16") != _sha16(np.ascontiguousarray(mask).tobytes()) or \
+            rec.get("oracle_c_sha256_16") != oracle_source_hash():
+        log("[bench] stored oracle inner counts are for another geometry or oracle; cpu_baseline omitted")
+        return None
+    N = mask.shape[0]
+    t0 = time.perf_counter()
+    o = oracle.Oracle(mask, (1.0, 0.0, 0.0))
+    t_asm = time.perf_counter() - t0
+    f = np.zeros((3, N, N, N))
+    f[0] = o.apply(oracle.OP_DIAG_A, None)[0] > 0
+    t0 = time.perf_counter()
+    _, itA = o.inner_solve(0, f, eps=1e-300, maxit=iters)
+    itA = abs(itA) if itA >= 0 else -itA - 1
+    tA = (time.perf_counter() - t0) / max(itA, 1)
+    b = o.apply(oracle.OP_B, np.random.default_rng(0).standard_normal((3, N, N, N)))
+    t0 = time.perf_counter()
+    _, itS = o.inner_solve(1, b, eps=1e-300, maxit=iters)
+    itS = abs(itS) if itS >= 0 else -itS - 1
+    tS = (time.perf_counter() - t0) / max(itS, 1)
+    mA = float(np.mean(rec["per_outer_A"]))
+    mS = float(np.mean(rec["per_outer_S"]))
+    outer = gpu_rep["outer_iters"]
+    nA = rec["start_A"] + outer * mA
+    nS = rec["start_S"] + outer * mS
+    est = nA * tA + nS * tS
     return {
         "value": 1.0 / est, "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
-        "sample": (f"oracle on the same {N}^3 geometry: one inner A solve ({itA} iterations, "
-                   f"{tA * 1e3:.1f} ms each) and {itS} inner SIMPLE iterations ({tS * 1e3:.1f} ms each), "
-                   f"scaled to the {gpu_rep['inner_A_iters']} + {gpu_rep['inner_S_iters']} inner iterations "
-                   f"of one solve (outer-loop vector work not counted); host {model or 'unknown CPU'}, "
-                   f"{os.cpu_count()} logical CPUs"),
+        "sample": (f"oracle (FP64, CSR over the active unknowns, Jacobi-PCG inner solves) on the same {N}^3 "
+                   f"geometry: {itA} inner A iterations ({tA * 1e3:.1f} ms each) and {itS} inner SIMPLE "
+                   f"iterations ({tS * 1e3:.1f} ms each) timed here; its own inner counts for this geometry "
+                   f"({rec['start_A']} A + {rec['start_S']} SIMPLE to start, then {mA:.0f} A + {mS:.0f} SIMPLE "
+                   f"per outer iteration, from its first {rec['outer_done']} outer iterations: "
+                   f"profiles/{os.path.basename(path)}) times the {outer} outer iterations of this solve = "
+                   f"{nA:.0f} A + {nS:.0f} SIMPLE iterations, {est:.0f} s per solve (assembly {t_asm:.1f} s and "
+                   f"outer-loop vector work not counted); host {host_cpu_model()}, {os.cpu_count()} logical CPUs"),
         "seconds_per_solve_est": est,
     }
+
+
+def large_solve(P, torch, workload="grf512"):
+    """One mixed-precision SIMPLE solve of a large workload (setup reported
+    beside the solve time, not in it)."""
+    desc, N, gen = WORKLOADS[workload]
+    log(f"[large] generating {desc}")
+    t0 = time.perf_counter()
+    mask = gen()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s = P.Stokes(mask, (1.0, 0.0, 0.0), stream=torch.cuda.current_stream().cuda_stream)
+    s.set_option("precision", 1)
+    s.set_option("progress", 40)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = s.info()
+    del mask
+    t0 = time.perf_counter()
+    rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    log(f"[large] {desc}: mixed solve {dt:.2f} s outer={rep['outer_iters']} k={rep['k_hat']:.12e}")
+    return {"workload": f"mixed FP32/FP64 SIMPLE solve, {desc}, force x, tol 1e-8", "N": N,
+            "solve_s": dt, "solves_per_s": 1.0 / dt, "setup_s": t_setup, "generate_s": t_gen,
+            "outer_iters": rep["outer_iters"], "inner_A_iters": rep["inner_A_iters"],
+            "inner_S_iters": rep["inner_S_iters"], "k_hat": rep["k_hat"], "rel_res": rep["rel_res"],
+            "div_norm": rep["div_norm"], "status": rep["status"], "porosity_effective": rep["porosity_effective"],
+            "components_kept": info["ncomp_kept"]}
 
 
 def generate_requests(n):
@@ -250,8 +371,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="spheres128", choices=sorted(WORKLOADS),
-                    help="geometry: the 128^3 spheres solve (default) or one of the large boxes")
+    ap.add_argument("--workload", default="tight256", choices=sorted(WORKLOADS),
+                    help="geometry: the 256^3 tight sphere pack (default), the 128^3 spheres or the 512^3 field")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the mixed-precision 512^3 solve reported beside the line")
+    ap.add_argument("--oracle-counts", action="store_true",
+                    help="CPU only: measure the oracle's own inner iteration counts on --workload for the "
+                         "CPU baseline and store them under profiles/")
     ap.add_argument("--precond", default="simple", choices=["simple", "uzawa"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--mixed-steps", type=int, default=3,
@@ -261,7 +387,8 @@ def main():
     ap.add_argument("--max-outer", type=int, default=0,
                     help="cap the outer iterations (short runs for hardware-counter profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference for the byte counters)")
+                    help="also run a plain 2 GiB device copy (reference for the byte counters; larger than "
+                         "the 256 MB Infinity Cache)")
     ap.add_argument("--requests", type=int, default=48,
                     help="serving requests run beside the solve benchmark (0 = skip)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
@@ -269,6 +396,9 @@ def main():
     ap.add_argument("--study", choices=["precond"],
                     help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries")
     args = ap.parse_args()
+    if args.oracle_counts:
+        measure_oracle_counts(args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this solver has no multi-GPU path",
               file=sys.stderr)
@@ -314,7 +444,8 @@ def main():
     if args.max_outer:
         s.set_option("max_outer", args.max_outer)
     if args.copy_calibration:
-        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+        # 2 GiB read + 2 GiB written per copy, far beyond the 256 MB Infinity Cache
+        src = torch.ones(256 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -435,14 +566,18 @@ def main():
         }
         log(f"[bench] mixed: {tm:.3f} s/solve outer={rm['outer_iters']} k={rm['k_hat']:.12e}")
     s.close()
+    if not args.no_large and args.workload != "grf512":
+        out["large_mixed_solve"] = large_solve(P, torch)
     if reqs:
         out["serving"] = serve(P, reqs, slots=args.serve_slots)
         log(f"[serve] {out['serving']['throughput_requests_per_s']:.2f} requests/s, latency p50 "
             f"{out['serving']['latency_ms']['p50']:.0f} ms p99 {out['serving']['latency_ms']['p99']:.0f} ms")
-    if not args.no_cpu_baseline and N <= 128:
+    if not args.no_cpu_baseline and N <= 256:
         log("[bench] timing the oracle on a bounded sample")
-        cb = cpu_baseline(mask, rep)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        cb = cpu_baseline(args.workload, mask, rep)
+        if cb:
+            out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+            out["cpu_baseline_seconds_per_solve_est"] = cb["seconds_per_solve_est"]
     print(json.dumps(out), flush=True)
 
 
