@@ -170,6 +170,35 @@ stokes_status stokes_setup_with_allocator(stokes_ctx **ctx, const uint8_t *mask,
                                           unsigned flags, void *stream, const stokes_allocator *alloc);
 
 /*
+ * stokes_setup_batch -- one context for `nmembers` geometries of the same
+ * size N (1 <= nmembers <= 32), the k-th from masks[k] (host pointers, read
+ * during the call), with the same force and flags, for callers that solve
+ * many small problems at once (the request server).  Every kernel launch of
+ * the context then advances all members: the launch's second grid dimension
+ * is the member, and each member's buffers sit at a fixed stride from the
+ * previous member's in one device allocation (stream-ordered on `stream`
+ * when it is not NULL).  Reductions and CG scalars stay per member, and a
+ * member that has finished a loop sits out the rest of it, so each member's
+ * result is bitwise the same whatever the other members are.
+ * stokes_solve runs the mixed-precision solve (option "precision" stays 1)
+ * for every member and returns the worst member status (its report is member
+ * 0's); stokes_batch_result reads each member's.  The operator test hooks
+ * (stokes_apply*) refuse batched contexts with STOKES_E_STATE.
+ * Errors as stokes_setup_ex, for any member; STOKES_E_ARG for a bad member
+ * count or a NULL mask.
+ */
+stokes_status stokes_setup_batch(stokes_ctx **ctx, const uint8_t *const *masks, int nmembers, int N,
+                                 const double force[3], unsigned flags, void *stream);
+
+/*
+ * stokes_batch_result -- member `member` of the last solve of a context made
+ * by stokes_setup_batch: its report, and (each may be NULL) its pressure (N^3
+ * doubles) and velocity (3 N^3 doubles) copied to host memory.
+ * STOKES_E_ARG for a bad member, STOKES_E_STATE before a solve.
+ */
+stokes_status stokes_batch_result(stokes_ctx *ctx, int member, stokes_report *report, double *p, double *u);
+
+/*
  * stokes_estimate_bytes -- upper bound of the device bytes a context for an
  * N^3 box holds (info[9] after setup, plus the FP32 vectors when precision =
  * 1 is used), with the component arrays at their 2048-component limit.

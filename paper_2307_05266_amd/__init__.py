@@ -11,6 +11,7 @@ its sources (csrc/), the build script and a thin ctypes binding.
 from .stokes import (  # noqa: F401
     Server,
     Stokes,
+    StokesBatch,
     StokesError,
     stokes_estimate_bytes,
     stokes_setup_on_stream,

@@ -47,15 +47,43 @@ constexpr int kZBatchA = 2;    // face kernels (three planes of unknowns per vox
 // partial slots of the inner CG loops
 constexpr int kRZ = 0, kZZ = 1, kDQ = 2, kNumSlots = 3;
 
+// Batched contexts: B members (independent geometries of one size) whose
+// device buffers sit at one fixed byte stride from each other; a launch covers
+// every member, with grid y = member, and each block shifts its pointers by
+// member * stride.  A plain context is one member with stride 0.
+constexpr int kMaxBatch = 32;
+
 struct Sweep {
     int N;
     int bxlog;        // BX = 1 << bxlog, BY = kBlock >> bxlog
     int gx, gy, gz;   // blocks along x, y and z
     int lz;           // z-planes per block
-    int nblk;         // gx * gy * gz
+    int nblk;         // gx * gy * gz (per member)
     int N2;           // N * N
     int n3;           // N^3 (< 2^31 for N <= 800)
+    int nbatch;       // members (grid y)
+    unsigned active;  // outer-loop kernels: bit m set = member m takes part
+    size_t bstride;   // bytes from one member's buffers to the next one's
 };
+
+// Per-member scalars of an outer-loop kernel (by value).
+struct MemberScalars {
+    double v[kMaxBatch];
+};
+
+template <class P>
+__device__ __forceinline__ void shift1(P& p, size_t o) {
+    if (p) p = reinterpret_cast<P>(reinterpret_cast<uintptr_t>(p) + o);
+}
+
+// Point each pointer at this block's member (grid y) of a batched context.
+template <class... P>
+__device__ __forceinline__ void shift_all(size_t o, P&... p) {
+    (shift1(p, o), ...);
+}
+
+// Outer-loop kernels skip the members that sit out the current step.
+__device__ __forceinline__ bool member_active(unsigned active) { return (active >> blockIdx.y) & 1u; }
 
 // Inner CG state, resident in device memory.  Scalars are written by block 0
 // only; rho is double-buffered by iteration parity because the other blocks
@@ -205,6 +233,7 @@ __device__ __forceinline__ int fluid_bit(const uint32_t* bits, int N, int wpr, i
 }
 
 __global__ void k_face_codes(Sweep s, const uint32_t* __restrict__ bits, int wpr, uint8_t* __restrict__ code) {
+    shift_all((size_t)blockIdx.y * s.bstride, bits, code);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const int N = s.N;
@@ -240,6 +269,7 @@ __device__ __forceinline__ double diag_Shat_cell(const uint8_t* __restrict__ cod
 }
 
 __global__ void k_inv_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ inv) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, inv);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -260,6 +290,7 @@ __device__ __forceinline__ double apply_A_face(const double* __restrict__ u, con
 
 __global__ void k_apply_A(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ u,
                           double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, u, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -275,6 +306,8 @@ __global__ void k_apply_A(Sweep s, const uint8_t* __restrict__ code, const doubl
 // (B^T p)(c, X) = p_X - p_{X - e_c} on active faces
 __global__ void k_apply_BT(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p,
                            double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     double* ox = out;
@@ -293,6 +326,8 @@ __global__ void k_apply_BT(Sweep s, const uint8_t* __restrict__ code, const doub
 // f - B^T p on active faces (right-hand side of the velocity recovery)
 __global__ void k_force_minus_BT(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p, double f0,
                                  double f1, double f2, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     double* ox = out;
@@ -310,6 +345,8 @@ __global__ void k_force_minus_BT(Sweep s, const uint8_t* __restrict__ code, cons
 
 // (B u)_X = sum_c [u(c, X) - u(c, X + e_c)]  (0 in solid cells by the invariant)
 __global__ void k_apply_B(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const double* ux = u;
@@ -335,6 +372,7 @@ __device__ __forceinline__ double apply_Shat_cell(const double pX, const double 
 
 __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p,
                              double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -344,6 +382,7 @@ __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const do
 }
 
 __global__ void k_diag_A(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -355,6 +394,7 @@ __global__ void k_diag_A(Sweep s, const uint8_t* __restrict__ code, double* __re
 }
 
 __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -365,6 +405,7 @@ __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* _
 
 // zero the entries that are not unknowns (inactive faces / solid cells)
 __global__ void k_mask_faces(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ u) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, u);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -377,6 +418,7 @@ __global__ void k_mask_faces(Sweep s, const uint8_t* __restrict__ code, double* 
 }
 
 __global__ void k_mask_cells(Sweep s, const uint32_t* __restrict__ bits, int wpr, double* __restrict__ p) {
+    shift_all((size_t)blockIdx.y * s.bstride, bits, p);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -512,6 +554,16 @@ __device__ __forceinline__ void face_tab_fill(FaceTab<T>& t) {
 template <class T>
 __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const double* b, double f0, double f1,
                            double f2, T* __restrict__ x, T* r, CgState* st, double* part, double eps, int maxit) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, b, x, r, st, part);
+    if (!member_active(s.active)) {
+        // this member sits the solve out: it is done before its first iteration
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->it = 0;
+            st->status = 0;
+            st->done = 1;
+        }
+        return;
+    }
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
@@ -551,6 +603,7 @@ __device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(cod
 template <class T>
 __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ r, T* __restrict__ d,
                           CgState* st, double* part, const T* __restrict__ zpre) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, r, d, st, part, zpre);
     if (st->done) return;
     double beta_d;
     int j;
@@ -594,6 +647,7 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __
 template <class T>
 __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __restrict__ x, T* __restrict__ r,
                              const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, x, r, d, q, st, part);
     if (st->done) return;
     double alpha_d;
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
@@ -646,6 +700,16 @@ __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __res
 template <class T>
 __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b, T* __restrict__ x, T* r,
                            CgState* st, double* part, double eps, int maxit) {
+    shift_all((size_t)blockIdx.y * s.bstride, invd, b, x, r, st, part);
+    if (!member_active(s.active)) {
+        // this member sits the solve out: it is done before its first iteration
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->it = 0;
+            st->status = 0;
+            st->done = 1;
+        }
+        return;
+    }
     const Column c = sweep_column(s);
     double acc[2] = {0.0, 0.0};
     if (c.valid) {
@@ -675,6 +739,7 @@ __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b,
 template <class T>
 __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restrict__ r, T* __restrict__ d,
                           CgState* st, double* part, const T* __restrict__ zpre) {
+    shift_all((size_t)blockIdx.y * s.bstride, invd, r, d, st, part, zpre);
     if (st->done) return;
     double beta_d;
     int j;
@@ -762,6 +827,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_cgS_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
                                                               const T* __restrict__ d, T* __restrict__ q,
                                                               CgState* st, double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
     if (st->done) return;
     __shared__ T tl[2][kTileMax];
     __shared__ FaceTab<T> ft;
@@ -805,6 +871,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_cgA_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
                                                               const T* __restrict__ d, T* __restrict__ q,
                                                               CgState* st, double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
     if (st->done) return;
     __shared__ T tl[2][3][kTileMax];
     __shared__ FaceTab<T> ft;
@@ -868,6 +935,7 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_tiled(Sweep s, const 
                                                                  const T* __restrict__ z, const T* __restrict__ din,
                                                                  T* __restrict__ dout, T* __restrict__ q, CgState* st,
                                                                  double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
     if (st->done) return;
     double beta_d;
     int j;
@@ -918,6 +986,7 @@ __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const 
                                                                  const T* __restrict__ z, const T* __restrict__ din,
                                                                  T* __restrict__ dout, T* __restrict__ q, CgState* st,
                                                                  double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
     if (st->done) return;
     double beta_d;
     int j;
@@ -980,6 +1049,7 @@ __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const 
 template <class T>
 __global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict__ x, T* __restrict__ r,
                              const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
+    shift_all((size_t)blockIdx.y * s.bstride, invd, x, r, d, q, st, part);
     if (st->done) return;
     double alpha_d;
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
@@ -1020,6 +1090,8 @@ __global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict_
 // ---- mixed-precision helpers -------------------------------------------------
 // out = in converted to FP64 (cells)
 __global__ void k_widen_cells(Sweep s, const float* __restrict__ in, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, in, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1029,6 +1101,7 @@ __global__ void k_widen_cells(Sweep s, const float* __restrict__ in, double* __r
 }
 
 __global__ void k_narrow_cells(Sweep s, const double* __restrict__ in, float* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, in, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1041,6 +1114,8 @@ __global__ void k_narrow_cells(Sweep s, const double* __restrict__ in, float* __
 // partials of (res, res) and (rhs, rhs) to out[3*b + 0..1]
 __global__ void k_residual_A(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ rhs,
                              const double* __restrict__ u, double* __restrict__ res, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, code, rhs, u, res, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
     if (c.valid) {
@@ -1065,7 +1140,10 @@ __global__ void k_residual_A(Sweep s, const uint8_t* __restrict__ code, const do
 }
 
 // u += a v with v in FP32 (faces)
-__global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* __restrict__ v, double a) {
+__global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* __restrict__ v, MemberScalars am) {
+    shift_all((size_t)blockIdx.y * s.bstride, u, v);
+    if (!member_active(s.active)) return;
+    const double a = am.v[blockIdx.y];
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1076,6 +1154,8 @@ __global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* _
 
 // (B v)_X with v in FP32, result in FP64
 __global__ void k_apply_B_f32(Sweep s, const float* __restrict__ u, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const float* ux = u;
@@ -1094,6 +1174,8 @@ __global__ void k_apply_B_f32(Sweep s, const float* __restrict__ u, double* __re
 // up to three dot products of cell vectors; per-block partials to out[3*b + q]
 __global__ void k_dots(Sweep s, const double* a0, const double* b0, const double* a1, const double* b1,
                        const double* a2, const double* b2, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, a0, b0, a1, b1, a2, b2, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
     if (c.valid) {
@@ -1111,6 +1193,8 @@ __global__ void k_dots(Sweep s, const double* a0, const double* b0, const double
 
 // sums of the three velocity planes; per-block partials to out[3*b + c]
 __global__ void k_face_sums(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
+    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
     if (c.valid) {
@@ -1128,7 +1212,10 @@ __global__ void k_face_sums(Sweep s, const double* __restrict__ u, double* __res
 
 // p += alpha d, r -= alpha q
 __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restrict__ r, const double* __restrict__ d,
-                               const double* __restrict__ q, double alpha) {
+                               const double* __restrict__ q, MemberScalars am) {
+    shift_all((size_t)blockIdx.y * s.bstride, p, r, d, q);
+    if (!member_active(s.active)) return;
+    const double alpha = am.v[blockIdx.y];
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1139,7 +1226,10 @@ __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restri
 }
 
 // u += a v on all three planes
-__global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __restrict__ v, double a) {
+__global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __restrict__ v, MemberScalars am) {
+    shift_all((size_t)blockIdx.y * s.bstride, u, v);
+    if (!member_active(s.active)) return;
+    const double a = am.v[blockIdx.y];
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1150,8 +1240,23 @@ __global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __re
     }
 }
 
+// dst = src (cells), for the members in s.active
+__global__ void k_copy_cells(Sweep s, double* __restrict__ dst, const double* __restrict__ src) {
+    shift_all((size_t)blockIdx.y * s.bstride, dst, src);
+    if (!member_active(s.active)) return;
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const int X = c.X0 + k * s.N2;
+        dst[X] = src[X];
+    }
+}
+
 // d = z + beta d
-__global__ void k_dir_cells(Sweep s, double* __restrict__ d, const double* __restrict__ z, double beta) {
+__global__ void k_dir_cells(Sweep s, double* __restrict__ d, const double* __restrict__ z, MemberScalars bm) {
+    shift_all((size_t)blockIdx.y * s.bstride, d, z);
+    if (!member_active(s.active)) return;
+    const double beta = bm.v[blockIdx.y];
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1179,7 +1284,9 @@ __device__ __forceinline__ int label_at(const uint16_t* label, const uint32_t* b
 
 __global__ void k_comp_sum(const double* __restrict__ x, const uint16_t* __restrict__ label,
                            const uint32_t* __restrict__ bits, int N, int wpr, int64_t n3, int K, int64_t chunk,
-                           double* __restrict__ part) {
+                           double* __restrict__ part, size_t bstride, unsigned active) {
+    shift_all((size_t)blockIdx.y * bstride, x, label, bits, part);
+    if (!member_active(active)) return;
     extern __shared__ double bins[];  // [kWaves][K]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int q = threadIdx.x; q < kWaves * K; q += kBlock) bins[q] = 0.0;
@@ -1213,7 +1320,9 @@ __global__ void k_comp_sum(const double* __restrict__ x, const uint16_t* __restr
 }
 
 __global__ void k_comp_mean(const double* __restrict__ part, int nblk, int K, const double* __restrict__ count,
-                            double* __restrict__ mean) {
+                            double* __restrict__ mean, size_t bstride, unsigned active) {
+    shift_all((size_t)blockIdx.y * bstride, part, count, mean);
+    if (!member_active(active)) return;
     const int L = blockIdx.x * kBlock + threadIdx.x;
     if (L >= K) return;
     double a = 0.0;
@@ -1223,7 +1332,9 @@ __global__ void k_comp_mean(const double* __restrict__ part, int nblk, int K, co
 
 __global__ void k_comp_sub(double* __restrict__ x, const uint16_t* __restrict__ label,
                            const uint32_t* __restrict__ bits, int N, int wpr, int64_t n3,
-                           const double* __restrict__ mean) {
+                           const double* __restrict__ mean, size_t bstride, unsigned active) {
+    shift_all((size_t)blockIdx.y * bstride, x, label, bits, mean);
+    if (!member_active(active)) return;
     for (int64_t X = (int64_t)blockIdx.x * kBlock + threadIdx.x; X < n3; X += (int64_t)gridDim.x * kBlock) {
         const int l = label_at(label, bits, N, wpr, X);
         if (l >= 0) x[X] -= mean[l];
@@ -1236,6 +1347,8 @@ __global__ void k_comp_sub(double* __restrict__ x, const uint16_t* __restrict__ 
 // in block order (bit-identical mean in every block) and subtracts the mean at
 // the fluid cells: two sweeps instead of three latency-bound kernels.
 __global__ void k_sum1(Sweep s, const double* __restrict__ x, double* __restrict__ part) {
+    shift_all((size_t)blockIdx.y * s.bstride, x, part);
+    if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
     if (c.valid)
@@ -1245,6 +1358,8 @@ __global__ void k_sum1(Sweep s, const double* __restrict__ x, double* __restrict
 
 __global__ void k_sub_mean1(Sweep s, double* __restrict__ x, const uint32_t* __restrict__ bits, int wpr,
                             const double* __restrict__ part, double inv_count) {
+    shift_all((size_t)blockIdx.y * s.bstride, x, bits, part);
+    if (!member_active(s.active)) return;
     const int slots[1] = {0};
     double tot[1];
     read_totals<1>(part, slots, s.nblk, tot);

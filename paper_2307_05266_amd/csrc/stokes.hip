@@ -84,6 +84,22 @@ struct stokes_ctx {
     unsigned setup_flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;                // the device current at setup
+    // batched context (stokes_setup_batch): nbatch members of one size, member
+    // m's buffers at m * bstride bytes from member 0's (a plain context: 1, 0)
+    int nbatch = 1;
+    size_t bstride = 0;
+    bool batch_api = false;        // set up by stokes_setup_batch (any member count)
+    char* slab = nullptr;          // batched: the members' common allocation
+    size_t slab_used = 0;          // bytes of member 0's part handed out so far
+    struct Member {
+        int64_t nfluid_in = 0, nfluid = 0, nsurf = 0;
+        int ncomp_all = 0, ncomp_kept = 0;
+        int64_t nface[3] = {0, 0, 0};
+    };
+    std::vector<Member> member;    // per member (plain: one)
+    std::vector<stokes_report> mrep;        // per member: report of the last solve
+    std::vector<std::vector<double>> mhist; // per member: history of the last solve
+    std::vector<int> m_it, m_status;        // per member: last inner solve's iterations, status
     double* noalloc_scratch = nullptr;  // this device's copy of `scratch` (stokes_apply_device_noalloc)
 
     // geometry summary
@@ -212,6 +228,9 @@ Sweep make_sweep(int N, int target_blocks) {
     if (N % 2 == 0 && (s.lz & 1)) ++s.lz;
     s.gz = (N + s.lz - 1) / s.lz;
     s.nblk = s.gx * s.gy * s.gz;
+    s.nbatch = 1;
+    s.active = 1u;
+    s.bstride = 0;
     return s;
 }
 
@@ -240,6 +259,17 @@ template <class T>
 stokes_status dev_alloc(stokes_ctx* c, T** ptr, size_t count) {
     void* m = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (c->slab) {
+        // batched: member 0's buffer at the next 256-byte boundary of its part
+        // of the slab; every member has its own at the same offset
+        const size_t off = (c->slab_used + 255) & ~(size_t)255;
+        if (off + bytes > c->bstride) return STOKES_E_NOMEM;
+        c->slab_used = off + bytes;
+        m = c->slab + off;
+        HIP_TRY(hipMemset2DAsync(m, c->bstride, 0, bytes, (size_t)c->nbatch, c->stream));
+        *ptr = static_cast<T*>(m);
+        return STOKES_OK;
+    }
     if (c->ext_alloc.alloc) {
         m = c->ext_alloc.alloc(bytes, (void*)c->stream, c->ext_alloc.user);
         if (!m) return STOKES_E_NOMEM;
@@ -277,7 +307,26 @@ void release(stokes_ctx* c) {
     c->host_part = nullptr;
 }
 
-dim3 grid_of(const Sweep& s) { return dim3((unsigned)s.nblk); }
+dim3 grid_of(const Sweep& s) { return dim3((unsigned)s.nblk, (unsigned)s.nbatch); }
+
+// bit mask of members 0 .. B-1
+unsigned all_members_of(int B) { return B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u); }
+
+// the same scalar for member 0 (plain contexts)
+MemberScalars ms1(double v) {
+    MemberScalars m{};
+    m.v[0] = v;
+    return m;
+}
+
+// The members' copy of a sweep (grid y = member, their buffers bstride apart).
+Sweep member_sweep(const stokes_ctx* c, Sweep s) {
+    s.nbatch = c->nbatch;
+    s.bstride = c->bstride;
+    s.active = all_members_of(c->nbatch);
+    return s;
+}
+
 
 // ---- inner solves -----------------------------------------------------------
 // With kernel timing on, every `timing`-th iteration of an inner solve runs
@@ -321,10 +370,14 @@ stokes_status collect_timing(stokes_ctx* c) {
     return STOKES_OK;
 }
 
-stokes_status read_state(stokes_ctx* c, int which, CgState* out) {
-    HIP_TRY(hipMemcpyAsync(c->host_state, c->cg + which, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+// Inner-CG state of every member (host_state[m]).
+stokes_status read_states(stokes_ctx* c, int which) {
+    if (c->nbatch == 1)
+        HIP_TRY(hipMemcpyAsync(c->host_state, c->cg + which, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    else
+        HIP_TRY(hipMemcpy2DAsync(c->host_state, sizeof(CgState), c->cg + which, c->bstride, sizeof(CgState),
+                                 (size_t)c->nbatch, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    *out = *c->host_state;
     return STOKES_OK;
 }
 
@@ -405,7 +458,7 @@ stokes_status run_inner(stokes_ctx* c, int which, const GraphKey& key, Body body
         }
     }
     int batch = first_batch(c, which);
-    CgState h{};
+    const int B = c->nbatch;
     for (;;) {
         for (int t = 0; t < (batch + 1) / 2; ++t) {
             c->time_iter = c->timing && (c->timing_seen[which]++ % c->timing) == 0;
@@ -417,13 +470,26 @@ stokes_status run_inner(stokes_ctx* c, int which, const GraphKey& key, Body body
             c->time_iter = false;
         }
         HIP_TRY(hipGetLastError());
-        ST_TRY(read_state(c, which, &h));
-        if (h.done) break;
+        ST_TRY(read_states(c, which));
+        bool all = true;
+        for (int m = 0; m < B; ++m) all = all && c->host_state[m].done;
+        if (all) break;
         batch = next_batch(c);
     }
-    c->last_it[which] = h.it;
-    *iters = h.it;
-    *status = h.status;
+    // per member: iterations and status (members that sat out report 0, 0)
+    int most = 0, worst = 0;
+    c->m_it.assign(B, 0);
+    c->m_status.assign(B, 0);
+    for (int m = 0; m < B; ++m) {
+        const CgState& h = c->host_state[m];
+        c->m_it[m] = h.it;
+        c->m_status[m] = h.status;
+        most = std::max(most, h.it);
+        if (h.status == -4 || (h.status == 1 && worst == 0)) worst = h.status;
+    }
+    c->last_it[which] = most;
+    *iters = most;
+    *status = worst;
     return STOKES_OK;
 }
 
@@ -534,8 +600,8 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     h.grid.clear();
     h.sweep.clear();
     for (int n : mg_plan(c->N, nb)) {
-        h.grid.push_back({n, n * n, n * n * n, nb});
-        h.sweep.push_back(make_sweep(n, c->mg_level_blocks));
+        h.grid.push_back({n, n * n, n * n * n, nb, c->bstride});
+        h.sweep.push_back(member_sweep(c, make_sweep(n, c->mg_level_blocks)));
     }
     const int L = (int)h.grid.size() - 1;
     if (L < 1) return STOKES_OK;
@@ -549,13 +615,13 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
     ST_TRY(dev_alloc(c, &h.r2, (size_t)nb * c->n3));
     ST_TRY(dev_alloc(c, &h.d2, (size_t)nb * c->n3));
     const int m1 = nb * h.grid[1].n3;
-    hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+    hipLaunchKernelGGL(k_mg_coarsen_fine<double>, dim3((m1 + kBlock - 1) / kBlock, c->nbatch), dim3(kBlock), 0, c->stream,
                        h.grid[0], h.grid[1], kind, c->code, h.l64[1].D, h.l64[1].Wx, h.l64[1].Wy, h.l64[1].Wz);
     for (int l = 1; l < L; ++l) {
         const auto& f = h.l64[l];
         const auto& t = h.l64[l + 1];
         const int m = nb * h.grid[l + 1].n3;
-        hipLaunchKernelGGL(k_mg_coarsen<double>, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+        hipLaunchKernelGGL(k_mg_coarsen<double>, dim3((m + kBlock - 1) / kBlock, c->nbatch), dim3(kBlock), 0, c->stream,
                            h.grid[l], h.grid[l + 1], f.D, f.Wx, f.Wy, f.Wz, t.D, t.Wx, t.Wy, t.Wz);
     }
     HIP_TRY(hipGetLastError());
@@ -576,7 +642,8 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
         const double* src[4] = {d.D, d.Wx, d.Wy, d.Wz};
         float* dst[4] = {lv.D, lv.Wx, lv.Wy, lv.Wz};
         for (int q = 0; q < 4; ++q)
-            hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m)), dim3(kBlock), 0, c->stream, m, src[q], dst[q]);
+            hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m), c->nbatch), dim3(kBlock), 0, c->stream, m, src[q],
+                               dst[q], c->bstride);
     }
     ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
     ST_TRY(dev_alloc(c, &h.r2_32, (size_t)h.nb * c->n3));
@@ -644,7 +711,7 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
         const T* bl = mg_view(h, l, T()).b;
         T* bn = mg_view(h, l + 1, T()).b;
         if (use_gs(l)) {
-            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
                                h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
         } else if (h.grid[l].n >= kMgTiledMinSide) {
             const Sweep& ls = h.sweep[l];
@@ -655,14 +722,14 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
         } else {
-            hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1))), dim3(kBlock), 0,
+            hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1)), c->nbatch), dim3(kBlock), 0,
                                c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
         }
     }
     // coarsest: Jacobi sweeps in one workgroup, result in x
     {
         auto v = mg_view(h, L, T());
-        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1), dim3(kMgCoarsestThreads), 0, c->stream, h.grid[L], ops[L],
+        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1, c->nbatch), dim3(kMgCoarsestThreads), 0, c->stream, h.grid[L], ops[L],
                            (const T*)v.b, v.x, omega, c->mg_coarse_sweeps, st);
     }
     // ascend: prolong the correction and postsmooth; the result of level l is
@@ -671,7 +738,7 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     for (int l = L - 1; l >= 1; --l) {
         auto v = mg_view(h, l, T());
         if (use_gs(l)) {
-            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l])), dim3(kGsThreads), 0, c->stream,
+            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
                                h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, v.y, st);
         } else if (h.grid[l].n >= kMgTiledMinSide) {
             const Sweep& ls = h.sweep[l];
@@ -682,7 +749,7 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
                 hipLaunchKernelGGL((k_mgc_tiled<T, 1, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
                                    h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
         } else {
-            hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l))), dim3(kBlock), 0, c->stream,
+            hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l)), c->nbatch), dim3(kBlock), 0, c->stream,
                                h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y,
                                st);
         }
@@ -839,13 +906,14 @@ stokes_status project_with(stokes_ctx* c, double* x, double* part, double* mean)
     }
     const int64_t chunk = ((c->n3 + kCompBlocks - 1) / kCompBlocks + 255) / 256 * 256;
     const int nb = (int)((c->n3 + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_comp_sum, dim3(nb), dim3(kBlock), (size_t)kWaves * K * sizeof(double), c->stream, x,
-                       c->label, c->bits, c->N, c->wpr, c->n3, K, chunk, part);
-    hipLaunchKernelGGL(k_comp_mean, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream, part, nb, K,
-                       c->comp_count, mean);
+    const unsigned B = (unsigned)c->nbatch, act = c->sw.active;
+    hipLaunchKernelGGL(k_comp_sum, dim3(nb, B), dim3(kBlock), (size_t)kWaves * K * sizeof(double), c->stream, x,
+                       c->label, c->bits, c->N, c->wpr, c->n3, K, chunk, part, c->bstride, act);
+    hipLaunchKernelGGL(k_comp_mean, dim3((K + kBlock - 1) / kBlock, B), dim3(kBlock), 0, c->stream, part, nb, K,
+                       c->comp_count, mean, c->bstride, act);
     const int subblocks = (int)std::min<int64_t>(4096, (c->n3 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_comp_sub, dim3(subblocks), dim3(kBlock), 0, c->stream, x, c->label, c->bits, c->N, c->wpr,
-                       c->n3, mean);
+    hipLaunchKernelGGL(k_comp_sub, dim3(subblocks, B), dim3(kBlock), 0, c->stream, x, c->label, c->bits, c->N, c->wpr,
+                       c->n3, mean, c->bstride, act);
     HIP_TRY(hipGetLastError());
     return STOKES_OK;
 }
@@ -856,14 +924,23 @@ stokes_status project(stokes_ctx* c, double* x) {
 }
 
 // per-block partials [3 * nblk] to the host, added there in block order
-stokes_status host_totals(stokes_ctx* c, double out[3]) {
+// Per member m: out[3 m + q] = its partials added in block order.
+stokes_status host_totals(stokes_ctx* c, double* out) {
     const int nb = c->sw.nblk;
-    HIP_TRY(hipMemcpyAsync(c->host_part, c->dpart, (size_t)3 * nb * sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
+    const size_t row = (size_t)3 * nb * sizeof(double);
+    if (c->nbatch == 1)
+        HIP_TRY(hipMemcpyAsync(c->host_part, c->dpart, row, hipMemcpyDeviceToHost, c->stream));
+    else
+        HIP_TRY(hipMemcpy2DAsync(c->host_part, row, c->dpart, c->bstride, row, (size_t)c->nbatch,
+                                 hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    out[0] = out[1] = out[2] = 0.0;
-    for (int b = 0; b < nb; ++b)
-        for (int q = 0; q < 3; ++q) out[q] += c->host_part[3 * b + q];
+    for (int m = 0; m < c->nbatch; ++m) {
+        const double* hp = c->host_part + (size_t)3 * nb * m;
+        double* o = out + 3 * m;
+        o[0] = o[1] = o[2] = 0.0;
+        for (int b = 0; b < nb; ++b)
+            for (int q = 0; q < 3; ++q) o[q] += hp[3 * b + q];
+    }
     return STOKES_OK;
 }
 
@@ -987,39 +1064,55 @@ const char* stokes_status_str(int s) {
     }
 }
 
-static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
-    Geometry g;
-    preprocess(mask, c->N, c->force, (c->setup_flags & STOKES_KEEP_ALL_COMPONENTS) != 0, g);
+// Set-up of a context with c->nbatch members (one: a plain context), the k-th
+// from masks[k].  A batched context keeps every member's buffers at the same
+// offsets of its part of one slab, so every buffer is allocated once, for
+// member 0, and the other members' copies follow at multiples of bstride.
+static stokes_status setup_impl(stokes_ctx* c, const uint8_t* const* masks) {
+    const int B = c->nbatch;
+    const int N = c->N;
+    const int64_t n3 = c->n3;
+    std::vector<Geometry> G(B);
+    c->member.assign(B, {});
+    int Kmax = 0;
+    for (int m = 0; m < B; ++m) {
+        preprocess(masks[m], N, c->force, (c->setup_flags & STOKES_KEEP_ALL_COMPONENTS) != 0, G[m]);
+        if (G[m].ncomp_kept > kMaxCompLds) return STOKES_E_LIMIT;
+        auto& mi = c->member[m];
+        mi.nfluid_in = G[m].nfluid_in;
+        mi.nfluid = G[m].nfluid;
+        mi.nsurf = G[m].nsurf;
+        mi.ncomp_all = G[m].ncomp_all;
+        mi.ncomp_kept = G[m].ncomp_kept;
+        Kmax = std::max(Kmax, G[m].ncomp_kept);
+    }
+    const Geometry& g = G[0];
     c->nfluid_in = g.nfluid_in;
     c->nfluid = g.nfluid;
     c->nsurf = g.nsurf;
     c->ncomp_all = g.ncomp_all;
-    c->ncomp_kept = g.ncomp_kept;
-    if (g.ncomp_kept > kMaxCompLds) return STOKES_E_LIMIT;
+    // batched: every member's projection covers Kmax components (a member with
+    // fewer has empty ones), through the labels
+    // (every context made by stokes_setup_batch does so, whatever its member
+    // count, so that a member's arithmetic does not depend on its batch)
+    const bool batched = B > 1 || c->batch_api;
+    c->ncomp_kept = batched ? Kmax : g.ncomp_kept;
 
-    const int N = c->N;
-    const int64_t n3 = c->n3;
     // one sweep for every kernel of an inner solve (the fused update and
     // restriction re-adds the stencil's partials, so both need one block count)
-    c->sw = make_sweep(N, c->sweep_blocks);
-    c->sw32 = make_sweep32(N, c->sweep_blocks);
+    c->sw = member_sweep(c, make_sweep(N, c->sweep_blocks));
+    c->sw32 = member_sweep(c, make_sweep32(N, c->sweep_blocks));
     if (c->sw.nblk > kMaxBlocks || c->sw32.nblk > kMaxBlocks) return STOKES_E_LIMIT;
     c->wpr = (N + 31) / 32;
 
-    // remaining-fluid bitmask
-    std::vector<uint32_t> bits((size_t)N * N * c->wpr, 0u);
-    for (int64_t row = 0; row < (int64_t)N * N; ++row)
-        for (int i = 0; i < N; ++i)
-            if (g.fluid[row * N + i]) bits[row * c->wpr + (i >> 5)] |= 1u << (i & 31);
-
-    const int K = std::max(1, g.ncomp_kept);
-    ST_TRY(dev_alloc(c, &c->bits, bits.size()));
+    const int K = std::max(1, c->ncomp_kept);
+    ST_TRY(dev_alloc(c, &c->bits, (size_t)N * N * c->wpr));
     ST_TRY(dev_alloc(c, &c->code, (size_t)n3));
     ST_TRY(dev_alloc(c, &c->comp_count, (size_t)K));
     ST_TRY(dev_alloc(c, &c->comp_part, (size_t)kCompBlocks * K));
     ST_TRY(dev_alloc(c, &c->proj_part, (size_t)kMaxBlocks));
     ST_TRY(dev_alloc(c, &c->comp_mean, (size_t)K));
-    if (g.ncomp_kept > 1) ST_TRY(dev_alloc(c, &c->label, (size_t)n3));
+    if (batched || g.ncomp_kept > 1) ST_TRY(dev_alloc(c, &c->label, (size_t)n3));
     for (double** f : {&c->fx, &c->fr, &c->fq, &c->u, &c->fd})
         ST_TRY(dev_alloc(c, f, (size_t)(3 * n3)));
     for (double** v : {&c->p, &c->r, &c->zs, &c->d, &c->q, &c->sr, &c->sq, &c->invdS, &c->sd})
@@ -1027,23 +1120,32 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     ST_TRY(dev_alloc(c, &c->cg, 2));
     ST_TRY(dev_alloc(c, &c->part, (size_t)kNumSlots * kMaxBlocks));
     ST_TRY(dev_alloc(c, &c->dpart, (size_t)3 * kMaxBlocks));
-    if (hipHostMalloc((void**)&c->host_state, sizeof(CgState)) != hipSuccess) return STOKES_E_NOMEM;
-    if (hipHostMalloc((void**)&c->host_part, 3 * kMaxBlocks * sizeof(double)) != hipSuccess) return STOKES_E_NOMEM;
+    if (hipHostMalloc((void**)&c->host_state, (size_t)B * sizeof(CgState)) != hipSuccess) return STOKES_E_NOMEM;
+    if (hipHostMalloc((void**)&c->host_part, (size_t)B * 3 * kMaxBlocks * sizeof(double)) != hipSuccess)
+        return STOKES_E_NOMEM;
 
-    std::vector<double> counts(K, 0.0);
-    for (int q = 0; q < g.ncomp_kept; ++q) counts[q] = (double)g.comp_size[q];
-    HIP_TRY(hipMemcpyAsync(c->bits, bits.data(), bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->comp_count, counts.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    if (c->label)
-        HIP_TRY(hipMemcpyAsync(c->label, g.label.data(), (size_t)n3 * sizeof(uint16_t), hipMemcpyHostToDevice,
-                               c->stream));
-    HIP_TRY(hipMemsetAsync(c->p, 0, (size_t)n3 * sizeof(double), c->stream));
-    HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
-    // zero every work vector once so that inactive entries start at 0
-    for (double* f : {c->fx, c->fr, c->fq, c->fd})
-        HIP_TRY(hipMemsetAsync(f, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
-    for (double* v : {c->r, c->zs, c->d, c->q, c->sr, c->sq, c->sd})
-        HIP_TRY(hipMemsetAsync(v, 0, (size_t)n3 * sizeof(double), c->stream));
+    // per member: remaining-fluid bitmask, component sizes, labels
+    std::vector<std::vector<uint32_t>> bits(B);
+    std::vector<std::vector<double>> counts(B);
+    for (int m = 0; m < B; ++m) {
+        bits[m].assign((size_t)N * N * c->wpr, 0u);
+        for (int64_t row = 0; row < (int64_t)N * N; ++row)
+            for (int i = 0; i < N; ++i)
+                if (G[m].fluid[row * N + i]) bits[m][row * c->wpr + (i >> 5)] |= 1u << (i & 31);
+        // components a member does not have count 1 (their mean is 0; no voxel carries them)
+        counts[m].assign(K, batched ? 1.0 : 0.0);
+        for (int q = 0; q < G[m].ncomp_kept; ++q) counts[m][q] = (double)G[m].comp_size[q];
+        const size_t o = (size_t)m * c->bstride;
+        HIP_TRY(hipMemcpyAsync((char*)c->bits + o, bits[m].data(), bits[m].size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync((char*)c->comp_count + o, counts[m].data(), K * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+        if (c->label) {
+            if (G[m].label.empty()) return STOKES_E_LIMIT;
+            HIP_TRY(hipMemcpyAsync((char*)c->label + o, G[m].label.data(), (size_t)n3 * sizeof(uint16_t),
+                                   hipMemcpyHostToDevice, c->stream));
+        }
+    }
     hipLaunchKernelGGL(k_face_codes, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->bits, c->wpr, c->code);
     hipLaunchKernelGGL(k_inv_diag_Shat, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->invdS);
     HIP_TRY(hipGetLastError());
@@ -1052,16 +1154,21 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* mask) {
     HIP_TRY(hipStreamSynchronize(c->stream));  // the host vectors above go out of scope
 
     // active faces per direction (host count from the remaining fluid)
-    for (int a = 0; a < 3; ++a) c->nface[a] = 0;
-    for (int k = 0; k < N; ++k)
-        for (int j = 0; j < N; ++j)
-            for (int i = 0; i < N; ++i) {
-                const int64_t X = i + (int64_t)N * (j + (int64_t)N * k);
-                if (!g.fluid[X]) continue;
-                if (g.fluid[((i + N - 1) % N) + (int64_t)N * (j + (int64_t)N * k)]) c->nface[0]++;
-                if (g.fluid[i + (int64_t)N * (((j + N - 1) % N) + (int64_t)N * k)]) c->nface[1]++;
-                if (g.fluid[i + (int64_t)N * (j + (int64_t)N * ((k + N - 1) % N))]) c->nface[2]++;
-            }
+    for (int m = 0; m < B; ++m) {
+        auto& nf = c->member[m].nface;
+        const std::vector<uint8_t>& fl = G[m].fluid;
+        nf[0] = nf[1] = nf[2] = 0;
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) {
+                    const int64_t X = i + (int64_t)N * (j + (int64_t)N * k);
+                    if (!fl[X]) continue;
+                    if (fl[((i + N - 1) % N) + (int64_t)N * (j + (int64_t)N * k)]) nf[0]++;
+                    if (fl[i + (int64_t)N * (((j + N - 1) % N) + (int64_t)N * k)]) nf[1]++;
+                    if (fl[i + (int64_t)N * (j + (int64_t)N * ((k + N - 1) % N))]) nf[2]++;
+                }
+    }
+    for (int a = 0; a < 3; ++a) c->nface[a] = c->member[0].nface[a];
     return STOKES_OK;
 }
 
@@ -1106,10 +1213,13 @@ stokes_status stokes_preprocess(const uint8_t* mask, int N, const double force[3
     return STOKES_OK;
 }
 
-static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
-                                  unsigned flags, hipStream_t stream, const stokes_allocator* alloc = nullptr) {
-    if (!out) return STOKES_E_ARG;
-    ST_TRY(check_inputs(mask, N, force, flags));
+static stokes_status ensure_mixed_buffers(stokes_ctx* c);
+
+static stokes_status setup_common(stokes_ctx** out, const uint8_t* const* masks, int B, int N,
+                                  const double force[3], unsigned flags, hipStream_t stream,
+                                  const stokes_allocator* alloc = nullptr, bool batch_api = false) {
+    if (!out || !masks || B < 1 || B > kMaxBatch) return STOKES_E_ARG;
+    for (int m = 0; m < B; ++m) ST_TRY(check_inputs(masks[m], N, force, flags));
     const int64_t n3 = (int64_t)N * N * N;
 
     stokes_ctx* c = new (std::nothrow) stokes_ctx();
@@ -1119,11 +1229,30 @@ static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, 
     for (int a = 0; a < 3; ++a) c->force[a] = force[a];
     c->setup_flags = flags;
     c->stream = stream;
+    c->nbatch = B;
+    c->batch_api = batch_api;
     if (alloc) c->ext_alloc = *alloc;
     else c->async_alloc = stream != nullptr;
-    stokes_status st;
+    stokes_status st = STOKES_OK;
+    if (B > 1) {
+        // one slab for all members: each member's part bounds a context's
+        // buffers (FP32 vectors included; 256-byte alignment of each buffer)
+        int64_t est = 0;
+        st = stokes_estimate_bytes(N, flags, 1, &est);
+        if (st == STOKES_OK) {
+            c->bstride = ((size_t)est + (size_t)(64 << 10) + 4095) & ~(size_t)4095;
+            char* slab = nullptr;
+            st = dev_alloc(c, &slab, c->bstride * (size_t)B);
+            c->slab = slab;
+        }
+    }
     try {
-        st = setup_impl(c, mask);
+        if (st == STOKES_OK) st = setup_impl(c, masks);
+        // a batched context runs the mixed-precision solve: its FP32 vectors now
+        if (st == STOKES_OK && batch_api) {
+            st = ensure_mixed_buffers(c);
+            c->precision = 1;
+        }
     } catch (const std::bad_alloc&) {
         st = STOKES_E_NOMEM;
     }
@@ -1141,23 +1270,31 @@ static stokes_status setup_common(stokes_ctx** out, const uint8_t* mask, int N, 
 }
 
 stokes_status stokes_setup_ex(stokes_ctx** out, const uint8_t* mask, int N, const double force[3], unsigned flags) {
-    return setup_common(out, mask, N, force, flags, nullptr);
+    return setup_common(out, &mask, 1, N, force, flags, nullptr);
 }
 
 stokes_status stokes_setup(stokes_ctx** out, const uint8_t* mask, int N, const double force[3]) {
-    return setup_common(out, mask, N, force, 0u, nullptr);
+    return setup_common(out, &mask, 1, N, force, 0u, nullptr);
 }
 
 stokes_status stokes_setup_on_stream(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
                                      unsigned flags, void* stream) {
     if (!stream) return STOKES_E_ARG;
-    return setup_common(out, mask, N, force, flags, (hipStream_t)stream);
+    return setup_common(out, &mask, 1, N, force, flags, (hipStream_t)stream);
+}
+
+stokes_status stokes_setup_batch(stokes_ctx** out, const uint8_t* const* masks, int nmembers, int N,
+                                 const double force[3], unsigned flags, void* stream) {
+    if (!masks || nmembers < 1 || nmembers > kMaxBatch) return STOKES_E_ARG;
+    for (int m = 0; m < nmembers; ++m)
+        if (!masks[m]) return STOKES_E_ARG;
+    return setup_common(out, masks, nmembers, N, force, flags, (hipStream_t)stream, nullptr, true);
 }
 
 stokes_status stokes_setup_with_allocator(stokes_ctx** out, const uint8_t* mask, int N, const double force[3],
                                           unsigned flags, void* stream, const stokes_allocator* alloc) {
     if (!alloc || !alloc->alloc || !alloc->free) return STOKES_E_ARG;
-    return setup_common(out, mask, N, force, flags, (hipStream_t)stream, alloc);
+    return setup_common(out, &mask, 1, N, force, flags, (hipStream_t)stream, alloc);
 }
 
 // Mirrors the allocations of setup_impl, build_mg, ensure_mixed_buffers and
@@ -1230,6 +1367,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "true_velocity") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->true_velocity = (int)v; }
     else if (k == "precision") {
         if (v != 0.0 && v != 1.0) return STOKES_E_ARG;
+        if (c->nbatch > 1 && v != 1.0) return STOKES_E_ARG;   // batched contexts solve in mixed precision
         if (v == 1.0) ST_TRY(ensure_mixed_buffers(c));
         c->precision = (int)v;
     }
@@ -1248,7 +1386,8 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         if (v < 8 || v > kMaxBlocks) return STOKES_E_ARG;
         c->mg_level_blocks = (int)v;
         for (MgHier* h : {&c->mgS, &c->mgA})
-            for (size_t l = 0; l < h->sweep.size(); ++l) h->sweep[l] = make_sweep(h->grid[l].n, c->mg_level_blocks);
+            for (size_t l = 0; l < h->sweep.size(); ++l)
+                h->sweep[l] = member_sweep(c, make_sweep(h->grid[l].n, c->mg_level_blocks));
     }
     else if (k == "mg_coarse_gs") { if (v != 0.0 && v != 1.0 && v != 2.0) return STOKES_E_ARG; c->mg_coarse_gs = (int)v; }
     else if (k == "sweep_blocks") {
@@ -1257,8 +1396,8 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
         const Sweep sw32 = make_sweep32(c->N, (int)v);
         if (sw.nblk > kMaxBlocks || sw32.nblk > kMaxBlocks) return STOKES_E_ARG;
         c->sweep_blocks = (int)v;
-        c->sw = sw;
-        c->sw32 = sw32;
+        c->sw = member_sweep(c, sw);
+        c->sw32 = member_sweep(c, sw32);
     }
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "fuse_dir_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_A = (int)v; }
@@ -1385,8 +1524,8 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
             }
             const double alpha = rz / dq;
             hipLaunchKernelGGL(k_outer_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->p, c->r, c->d, c->q,
-                               alpha);
-            hipLaunchKernelGGL(k_axpy_faces, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx, -alpha);
+                               ms1(alpha));
+            hipLaunchKernelGGL(k_axpy_faces, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx, ms1(-alpha));
             HIP_TRY(hipGetLastError());
             ST_TRY(project(c, c->r));
             if (precond == STOKES_SIMPLE) {
@@ -1408,7 +1547,7 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
             if (!stop) {
                 beta = dd[0] / rz;
                 rz = dd[0];
-                hipLaunchKernelGGL(k_dir_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->d, z, beta);
+                hipLaunchKernelGGL(k_dir_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->d, z, ms1(beta));
                 HIP_TRY(hipGetLastError());
             }
             alphas.push_back(alpha);
@@ -1472,173 +1611,350 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
 // with the refinement of u and a fresh true residual.  The solve stops when the
 // true residual meets tol.
 // ---------------------------------------------------------------------------
-// u <- A^{-1}(f - B^T p) to eps_refine, starting from the current u.
-static stokes_status refine_velocity(stokes_ctx* c, int64_t* totA, int* inner_status) {
-    const Sweep& s = c->sw;
-    hipLaunchKernelGGL(k_force_minus_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->p, c->force[0],
-                       c->force[1], c->force[2], c->fr);
+// Members that the outer-loop kernels (and the first kernel of each inner
+// solve) work on; the others sit the step out.
+static void set_active(stokes_ctx* c, unsigned mask) {
+    c->sw.active = mask;
+    c->sw32.active = mask;
+}
+
+static bool has(unsigned mask, int m) { return (mask >> m) & 1u; }
+
+// zero `bytes` of a per-member buffer in every member
+static stokes_status zero_members(stokes_ctx* c, void* p, size_t bytes) {
+    if (c->nbatch == 1) HIP_TRY(hipMemsetAsync(p, 0, bytes, c->stream));
+    else HIP_TRY(hipMemset2DAsync(p, c->bstride, 0, bytes, (size_t)c->nbatch, c->stream));
+    return STOKES_OK;
+}
+
+// Per-member state of the mixed-precision solve.
+struct MixedMember {
+    int k = 0, cycle = 0;
+    double r0 = 0.0, z0 = 0.0, rz = 0.0, target = 0.0, rel = 0.0, relz = 0.0, g_floor = 0.0;
+    int status = STOKES_OK;
+    int inner_status = 0;
+    unsigned flags = 0;
+    int64_t totA = 0, totS = 0;
+    std::vector<double> alphas, betas;   // first cycle only: a restart starts a new Krylov space
+};
+
+// u <- A^{-1}(f - B^T p) to eps_refine, starting from the current u, for the
+// members in `mask` (each refines until its own residual meets the tolerance).
+static stokes_status refine_velocity(stokes_ctx* c, unsigned mask, std::vector<MixedMember>& M) {
+    const int B = c->nbatch;
+    set_active(c, mask);
+    hipLaunchKernelGGL(k_force_minus_BT, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->p,
+                       c->force[0], c->force[1], c->force[2], c->fr);
     HIP_TRY(hipGetLastError());
-    for (int round = 0;; ++round) {
-        hipLaunchKernelGGL(k_residual_A, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->fr, c->u, c->fq,
-                           c->dpart);
+    std::vector<double> t(3 * (size_t)B);
+    MemberScalars one{};
+    for (int m = 0; m < B; ++m) one.v[m] = 1.0;
+    unsigned todo = mask;
+    for (int round = 0; todo; ++round) {
+        set_active(c, todo);
+        hipLaunchKernelGGL(k_residual_A, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->fr, c->u,
+                           c->fq, c->dpart);
         HIP_TRY(hipGetLastError());
-        double t[3];
-        ST_TRY(host_totals(c, t));
-        const double rel = t[1] > 0.0 ? std::sqrt(t[0] / t[1]) : 0.0;
-        if (!std::isfinite(rel)) return STOKES_E_BREAKDOWN;
-        if (rel < c->eps_refine || round >= c->max_refine) break;
+        ST_TRY(host_totals(c, t.data()));
+        unsigned next = 0;
+        for (int m = 0; m < B; ++m) {
+            if (!has(todo, m)) continue;
+            const double rel = t[3 * m + 1] > 0.0 ? std::sqrt(t[3 * m] / t[3 * m + 1]) : 0.0;
+            if (!std::isfinite(rel)) {
+                M[m].status = STOKES_E_BREAKDOWN;
+                continue;
+            }
+            if (!(rel < c->eps_refine || round >= c->max_refine)) next |= 1u << m;
+        }
+        todo = next;
+        if (!todo) break;
+        set_active(c, todo);
         int it = 0, st = 0;
         ST_TRY(inner_A<float>(c, bufA32(c), c->fq, c->eps_A32, &it, &st));
-        *totA += it;
-        if (st == -4) *inner_status = -4;
-        hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx32, 1.0);
+        for (int m = 0; m < B; ++m) {
+            if (!has(todo, m)) continue;
+            M[m].totA += c->m_it[m];
+            if (c->m_status[m] == -4) M[m].inner_status = -4;
+        }
+        set_active(c, todo);
+        hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->u, c->fx32, one);
         HIP_TRY(hipGetLastError());
     }
     return STOKES_OK;
 }
 
-// z <- SIMPLE^+ r in FP32 (widened and projected), or z = r for Uzawa
-static stokes_status mixed_precond(stokes_ctx* c, stokes_precond precond, int64_t* totS, int* inner_status) {
+// z <- SIMPLE^+ r in FP32 (widened and projected), or z = r for Uzawa, for the
+// members in `mask`
+static stokes_status mixed_precond(stokes_ctx* c, stokes_precond precond, unsigned mask, std::vector<MixedMember>& M) {
+    set_active(c, mask);
     if (precond == STOKES_UZAWA) {
-        HIP_TRY(hipMemcpyAsync(c->zs, c->r, (size_t)c->n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        hipLaunchKernelGGL(k_copy_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->zs,
+                           (const double*)c->r);
+        HIP_TRY(hipGetLastError());
         return STOKES_OK;
     }
     int it = 0, st = 0;
     ST_TRY(inner_S<float>(c, bufS32(c), c->r, c->eps_S32, &it, &st));
-    *totS += it;
-    if (st == -4) *inner_status = -4;
+    for (int m = 0; m < c->nbatch; ++m) {
+        if (!has(mask, m)) continue;
+        M[m].totS += c->m_it[m];
+        if (c->m_status[m] == -4) M[m].inner_status = -4;
+    }
+    set_active(c, mask);
     hipLaunchKernelGGL(k_widen_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->zs32, c->zs);
     HIP_TRY(hipGetLastError());
     return project(c, c->zs);
 }
 
+// Defect correction around a flexible outer CG, for every member of the
+// context at once (one member: a plain context).  Each cycle starts from the
+// true residual r = g - S p = B u, u = A^{-1}(f - B^T p) held in FP64 and
+// refined to eps_refine (FP32 CG sweeps on FP64 residuals); inside a cycle the
+// outer CG (flexible beta = (z_k+1, r_k+1 - r_k) / (z_k, r_k), Notay's FCG,
+// which tolerates the inexact FP32 preconditioner and S) reduces the recursive
+// residual by cycle_rtol, updating p and the recursive velocity; the cycle ends
+// with the refinement of u and a fresh true residual.  A member stops when its
+// true residual meets tol.  The members run in lockstep: every step is one
+// launch per kernel for all members still in that step; a member that has
+// left a loop sits out its remaining steps, so its arithmetic is exactly
+// that of a solve of its own.
 static stokes_status solve_mixed(stokes_ctx* c, stokes_precond precond, double tol) {
-    stokes_report& R = c->rep;
-    const Sweep& s = c->sw;
+    const int B = c->nbatch;
     const int64_t n3 = c->n3;
     const double N2 = (double)c->N * (double)c->N;
     ST_TRY(ensure_mixed_buffers(c));
     double* z = c->zs;        // FP64 preconditioned residual
     double* r_old = c->sr;    // FP64 previous residual (flexible beta)
-    int64_t totA = 0, totS = 0;
-    int inner_status = 0, status = STOKES_OK;
-    HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
-    ST_TRY(refine_velocity(c, &totA, &inner_status));
-    double g_floor = 0.0;
-    ST_TRY(rhs_floor(c, c->eps_refine, &g_floor));
-    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
-    HIP_TRY(hipGetLastError());
-    ST_TRY(project(c, c->r));
-    double dd[3];
-    ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd));
-    const double r0 = std::sqrt(dd[0]);
-    R.r0_norm = r0;
-    double rel = 0.0, relz = 0.0, z0 = 0.0;
-    int k = 0;
-    int cycle = 0;
-    std::vector<double> alphas, betas;   // first cycle only: a restart starts a new Krylov space
-    if (!(r0 > g_floor)) {
-        R.flags |= STOKES_FLAG_ZERO_RHS;
-    } else {
-        bool done = false;
-        for (; !done && status >= 0; ++cycle) {
-            // one defect-correction cycle on the current true residual
-            ST_TRY(mixed_precond(c, precond, &totS, &inner_status));
-            ST_TRY(dots(c, c->r, z, c->r, c->r, z, z, dd));
-            double rz = dd[0];
-            const double rs = std::sqrt(dd[1]);
-            if (z0 == 0.0) z0 = std::sqrt(dd[2]);
-            const double target = std::max(tol * r0, c->cycle_rtol * rs);
-            HIP_TRY(hipMemcpyAsync(c->d, z, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-            for (;;) {
-                if (k >= c->max_outer) { status = STOKES_NOT_CONVERGED; break; }
-                const int64_t a0 = totA, s0 = totS;
-                hipLaunchKernelGGL(k_apply_BT, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code, c->d, c->fr);
-                HIP_TRY(hipGetLastError());
-                int it = 0, st = 0;
-                ST_TRY(inner_A<float>(c, bufA32(c), c->fr, c->eps_A32, &it, &st));
-                totA += it;
-                if (st == -4) inner_status = -4;
-                hipLaunchKernelGGL(k_apply_B_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->fx32, c->q);
-                HIP_TRY(hipGetLastError());
-                ST_TRY(dots(c, c->d, c->q, nullptr, nullptr, nullptr, nullptr, dd));
-                const double dq = dd[0];
-                if (!(dq > 0.0) || !std::isfinite(dq)) { status = STOKES_E_BREAKDOWN; break; }
-                const double alpha = rz / dq;
-                HIP_TRY(hipMemcpyAsync(r_old, c->r, (size_t)n3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-                hipLaunchKernelGGL(k_outer_update, grid_of(s), dim3(kBlock), 0, c->stream, s, c->p, c->r, c->d, c->q,
-                                   alpha);
-                hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->fx32, -alpha);
-                HIP_TRY(hipGetLastError());
-                ST_TRY(project(c, c->r));
-                ST_TRY(mixed_precond(c, precond, &totS, &inner_status));
-                ++k;
-                ST_TRY(dots(c, z, c->r, z, r_old, c->r, c->r, dd));
-                const double rn = std::sqrt(dd[2]);
-                double zz[3];
-                ST_TRY(dots(c, z, z, nullptr, nullptr, nullptr, nullptr, zz));
-                rel = rn / r0;
-                relz = std::sqrt(zz[0]) / z0;
-                if (!std::isfinite(rel)) { status = STOKES_E_BREAKDOWN; break; }
-                const bool stop = rn <= target;
-                double beta = 0.0;
-                if (!stop) {
-                    beta = (dd[0] - dd[1]) / rz;   // flexible (Notay) beta
-                    rz = dd[0];
-                    hipLaunchKernelGGL(k_dir_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->d, z, beta);
-                    HIP_TRY(hipGetLastError());
-                }
-                if (cycle == 0) {
-                    alphas.push_back(alpha);
-                    if (!stop) betas.push_back(beta);
-                }
-                double sums[3], mean[3];
-                ST_TRY(face_sums(c, c->u, sums));
-                const double kk = kvox_of(c, sums, mean) / N2;
-                c->hist.insert(c->hist.end(),
-                               {rel, relz, kk, (double)(totA - a0), (double)(totS - s0), alpha, beta, 0.0});
-                report_progress(c, k, rel, kk);
-                if (stop) break;
+    std::vector<MixedMember> M(B);
+    c->mhist.assign(B, {});
+    unsigned live = 0;        // members with conducting fluid
+    for (int m = 0; m < B; ++m) {
+        if (c->member[m].nfluid > 0) live |= 1u << m;
+        else M[m].flags |= STOKES_FLAG_NO_FLOW;
+    }
+    ST_TRY(zero_members(c, c->p, (size_t)n3 * sizeof(double)));
+    ST_TRY(zero_members(c, c->u, (size_t)(3 * n3) * sizeof(double)));
+    std::vector<double> dd(3 * (size_t)B), zz(3 * (size_t)B), sums(3 * (size_t)B);
+    auto drop = [&](unsigned& mask) {   // members that failed or hit a cap leave `mask`
+        for (int m = 0; m < B; ++m)
+            if (has(mask, m) && (M[m].status < 0 || M[m].status == STOKES_NOT_CONVERGED)) mask &= ~(1u << m);
+    };
+    unsigned going = live;
+    if (going) ST_TRY(refine_velocity(c, going, M));
+    drop(going);
+    if (going) {
+        // g counts as zero below zero_rhs_factor * eps_refine * sqrt(f . u0)
+        set_active(c, going);
+        ST_TRY(face_sums(c, c->u, sums.data()));
+        for (int m = 0; m < B; ++m) {
+            double fu = 0.0;
+            for (int a = 0; a < 3; ++a) fu += c->force[a] * sums[3 * m + a];
+            M[m].g_floor = fu > 0.0 ? c->zero_rhs_factor * c->eps_refine * std::sqrt(fu) : 0.0;
+        }
+        hipLaunchKernelGGL(k_apply_B, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->u, c->r);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(project(c, c->r));
+        ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd.data()));
+        for (int m = 0; m < B; ++m) {
+            if (!has(going, m)) continue;
+            M[m].r0 = std::sqrt(dd[3 * m]);
+            if (!(M[m].r0 > M[m].g_floor)) {
+                M[m].flags |= STOKES_FLAG_ZERO_RHS;
+                going &= ~(1u << m);
             }
-            if (status < 0 || status == STOKES_NOT_CONVERGED) break;
-            // the true residual of the new pressure
-            ST_TRY(refine_velocity(c, &totA, &inner_status));
-            hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
-            HIP_TRY(hipGetLastError());
-            ST_TRY(project(c, c->r));
-            ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd));
-            rel = std::sqrt(dd[0]) / r0;
-            if (!c->hist.empty()) c->hist[c->hist.size() - 8] = rel;   // the cycle's last entry: true residual
-            if (rel < tol) done = true;
         }
     }
-    ST_TRY(project(c, c->p));
-    if (status >= 0 && inner_status == -4) status = STOKES_E_BREAKDOWN;
-
-    double sums[3], mean[3];
-    ST_TRY(face_sums(c, c->u, sums));
-    R.k_vox = kvox_of(c, sums, mean);
-    R.k_hat = R.k_vox / N2;
-    for (int a = 0; a < 3; ++a) R.mean_u[a] = mean[a];
-    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->q);
-    HIP_TRY(hipGetLastError());
-    double dv[3];
-    ST_TRY(dots(c, c->q, c->q, nullptr, nullptr, nullptr, nullptr, dv));
-    R.div_norm = std::sqrt(dv[0]);
-    R.outer_iters = k;
-    R.inner_A_iters = (int)totA;
-    R.inner_S_iters = (int)totS;
-    R.rel_res = rel;
-    R.rel_res_prec = relz;
-    if (!alphas.empty()) {
-        betas.resize(alphas.size() - 1 < betas.size() ? alphas.size() - 1 : betas.size());
-        lanczos_extremes(alphas, betas, &R.ritz_min, &R.ritz_max);
-        R.cond_est = R.ritz_max / R.ritz_min;
+    std::vector<double> alpha(B, 0.0);
+    std::vector<int64_t> a0(B), s0(B);
+    while (going) {
+        // one defect-correction cycle on the current true residual
+        ST_TRY(mixed_precond(c, precond, going, M));
+        set_active(c, going);
+        ST_TRY(dots(c, c->r, z, c->r, c->r, z, z, dd.data()));
+        for (int m = 0; m < B; ++m) {
+            if (!has(going, m)) continue;
+            MixedMember& q = M[m];
+            q.rz = dd[3 * m];
+            const double rs = std::sqrt(dd[3 * m + 1]);
+            if (q.z0 == 0.0) q.z0 = std::sqrt(dd[3 * m + 2]);
+            q.target = std::max(tol * q.r0, c->cycle_rtol * rs);
+        }
+        hipLaunchKernelGGL(k_copy_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->d, (const double*)z);
+        HIP_TRY(hipGetLastError());
+        unsigned inner = going;
+        while (inner) {
+            for (int m = 0; m < B; ++m)
+                if (has(inner, m) && M[m].k >= c->max_outer) M[m].status = STOKES_NOT_CONVERGED;
+            drop(inner);
+            if (!inner) break;
+            for (int m = 0; m < B; ++m) {
+                a0[m] = M[m].totA;
+                s0[m] = M[m].totS;
+            }
+            set_active(c, inner);
+            hipLaunchKernelGGL(k_apply_BT, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->d, c->fr);
+            HIP_TRY(hipGetLastError());
+            int it = 0, st = 0;
+            ST_TRY(inner_A<float>(c, bufA32(c), c->fr, c->eps_A32, &it, &st));
+            for (int m = 0; m < B; ++m) {
+                if (!has(inner, m)) continue;
+                M[m].totA += c->m_it[m];
+                if (c->m_status[m] == -4) M[m].inner_status = -4;
+            }
+            set_active(c, inner);
+            hipLaunchKernelGGL(k_apply_B_f32, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->fx32, c->q);
+            HIP_TRY(hipGetLastError());
+            ST_TRY(dots(c, c->d, c->q, nullptr, nullptr, nullptr, nullptr, dd.data()));
+            MemberScalars am{}, nam{};
+            for (int m = 0; m < B; ++m) {
+                if (!has(inner, m)) continue;
+                const double dq = dd[3 * m];
+                if (!(dq > 0.0) || !std::isfinite(dq)) {
+                    M[m].status = STOKES_E_BREAKDOWN;
+                    continue;
+                }
+                alpha[m] = M[m].rz / dq;
+                am.v[m] = alpha[m];
+                nam.v[m] = -alpha[m];
+            }
+            drop(inner);
+            if (!inner) break;
+            set_active(c, inner);
+            hipLaunchKernelGGL(k_copy_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, r_old,
+                               (const double*)c->r);
+            hipLaunchKernelGGL(k_outer_update, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->p, c->r, c->d,
+                               c->q, am);
+            hipLaunchKernelGGL(k_axpy_faces_f32, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->u, c->fx32,
+                               nam);
+            HIP_TRY(hipGetLastError());
+            ST_TRY(project(c, c->r));
+            ST_TRY(mixed_precond(c, precond, inner, M));
+            set_active(c, inner);
+            ST_TRY(dots(c, z, c->r, z, r_old, c->r, c->r, dd.data()));
+            ST_TRY(dots(c, z, z, nullptr, nullptr, nullptr, nullptr, zz.data()));
+            unsigned cont = 0, noted = 0;
+            MemberScalars bm{};
+            for (int m = 0; m < B; ++m) {
+                if (!has(inner, m)) continue;
+                MixedMember& q = M[m];
+                ++q.k;
+                const double rn = std::sqrt(dd[3 * m + 2]);
+                q.rel = rn / q.r0;
+                q.relz = std::sqrt(zz[3 * m]) / q.z0;
+                if (!std::isfinite(q.rel)) {
+                    q.status = STOKES_E_BREAKDOWN;
+                    continue;
+                }
+                noted |= 1u << m;
+                const bool stop = rn <= q.target;
+                double beta = 0.0;
+                if (!stop) {
+                    beta = (dd[3 * m] - dd[3 * m + 1]) / q.rz;   // flexible (Notay) beta
+                    q.rz = dd[3 * m];
+                    bm.v[m] = beta;
+                    cont |= 1u << m;
+                }
+                if (q.cycle == 0) {
+                    q.alphas.push_back(alpha[m]);
+                    if (!stop) q.betas.push_back(beta);
+                }
+                c->mhist[m].insert(c->mhist[m].end(), {q.rel, q.relz, 0.0, (double)(q.totA - a0[m]),
+                                                       (double)(q.totS - s0[m]), alpha[m], beta, 0.0});
+            }
+            if (cont) {
+                set_active(c, cont);
+                hipLaunchKernelGGL(k_dir_cells, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->d, z, bm);
+                HIP_TRY(hipGetLastError());
+            }
+            if (noted) {
+                // permeability of the recursive velocity, per iteration
+                set_active(c, noted);
+                ST_TRY(face_sums(c, c->u, sums.data()));
+                for (int m = 0; m < B; ++m) {
+                    if (!has(noted, m)) continue;
+                    double mean[3];
+                    const double kk = kvox_of(c, &sums[3 * m], mean) / N2;
+                    c->mhist[m][c->mhist[m].size() - 6] = kk;
+                    if (B == 1) report_progress(c, M[m].k, M[m].rel, kk);
+                }
+            }
+            inner = cont;
+            drop(going);
+        }
+        drop(going);
+        if (!going) break;
+        // the true residual of the new pressure
+        ST_TRY(refine_velocity(c, going, M));
+        drop(going);
+        if (!going) break;
+        set_active(c, going);
+        hipLaunchKernelGGL(k_apply_B, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->u, c->r);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(project(c, c->r));
+        ST_TRY(dots(c, c->r, c->r, nullptr, nullptr, nullptr, nullptr, dd.data()));
+        for (int m = 0; m < B; ++m) {
+            if (!has(going, m)) continue;
+            MixedMember& q = M[m];
+            q.rel = std::sqrt(dd[3 * m]) / q.r0;
+            auto& h = c->mhist[m];
+            if (!h.empty()) h[h.size() - 8] = q.rel;   // the cycle's last entry: true residual
+            ++q.cycle;
+            if (q.rel < tol) going &= ~(1u << m);
+        }
     }
-    R.status = status;
+    // results of every member with conducting fluid
+    std::vector<double> div(3 * (size_t)B, 0.0);
+    if (live) {
+        set_active(c, live);
+        ST_TRY(project(c, c->p));
+        ST_TRY(face_sums(c, c->u, sums.data()));
+        hipLaunchKernelGGL(k_apply_B, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->u, c->q);
+        HIP_TRY(hipGetLastError());
+        ST_TRY(dots(c, c->q, c->q, nullptr, nullptr, nullptr, nullptr, div.data()));
+    }
+    set_active(c, all_members_of(B));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->mrep.assign(B, stokes_report{});
+    int worst = STOKES_OK;
+    for (int m = 0; m < B; ++m) {
+        MixedMember& q = M[m];
+        stokes_report& R = c->mrep[m];
+        const auto& g = c->member[m];
+        R.n_components = g.ncomp_all;
+        R.n_components_kept = g.ncomp_kept;
+        R.porosity = (double)g.nfluid_in / (double)n3;
+        R.porosity_effective = (double)g.nfluid / (double)n3;
+        R.stv_ratio = g.nfluid_in ? (double)g.nsurf / (double)g.nfluid_in : 0.0;
+        R.cond_est = R.ritz_min = R.ritz_max = std::nan("");
+        R.flags = q.flags;
+        if (q.status >= 0 && q.inner_status == -4) q.status = STOKES_E_BREAKDOWN;
+        if (has(live, m)) {
+            double mean[3];
+            R.k_vox = kvox_of(c, &sums[3 * m], mean);
+            R.k_hat = R.k_vox / N2;
+            for (int a = 0; a < 3; ++a) R.mean_u[a] = mean[a];
+            R.div_norm = std::sqrt(div[3 * m]);
+        }
+        R.r0_norm = q.r0;
+        R.outer_iters = q.k;
+        R.inner_A_iters = (int)q.totA;
+        R.inner_S_iters = (int)q.totS;
+        R.rel_res = q.rel;
+        R.rel_res_prec = q.relz;
+        if (!q.alphas.empty()) {
+            q.betas.resize(q.alphas.size() - 1 < q.betas.size() ? q.alphas.size() - 1 : q.betas.size());
+            lanczos_extremes(q.alphas, q.betas, &R.ritz_min, &R.ritz_max);
+            R.cond_est = R.ritz_max / R.ritz_min;
+        }
+        R.status = q.status;
+        if (q.status < 0) worst = std::min(worst, q.status);
+        else if (q.status > 0 && worst == STOKES_OK) worst = q.status;
+    }
+    c->rep = c->mrep[0];
+    c->hist = c->mhist[0];
     ST_TRY(collect_timing(c));
-    c->have_solution = status >= 0;
-    return (stokes_status)status;
+    c->have_solution = B > 1 || worst >= 0;
+    return (stokes_status)worst;
 }
 
 stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, stokes_report* report) {
@@ -1649,13 +1965,31 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     c->t_solve0 = t0;
     stokes_status st;
     try {
-        st = solve_impl(c, precond, tol);
+        // a batched context solves all of its members at once (mixed precision)
+        st = c->batch_api ? solve_mixed(c, precond, tol) : solve_impl(c, precond, tol);
     } catch (const std::bad_alloc&) {
         st = STOKES_E_NOMEM;
     }
-    c->rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->rep.seconds = secs;
+    for (auto& r : c->mrep) r.seconds = secs;
     if (report) *report = c->rep;
     return st;
+}
+
+stokes_status stokes_batch_result(stokes_ctx* c, int member, stokes_report* report, double* p, double* u) {
+    if (!c || member < 0 || member >= c->nbatch) return STOKES_E_ARG;
+    if (!c->have_solution || (int)c->mrep.size() != c->nbatch) return STOKES_E_STATE;
+    if (report) *report = c->mrep[member];
+    const size_t o = (size_t)member * c->bstride;
+    if (p)
+        HIP_TRY(hipMemcpyAsync(p, (const char*)c->p + o, (size_t)c->n3 * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+    if (u)
+        HIP_TRY(hipMemcpyAsync(u, (const char*)c->u + o, (size_t)(3 * c->n3) * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return STOKES_OK;
 }
 
 stokes_status stokes_permeability(stokes_ctx* c, double* k_hat) {
@@ -1744,6 +2078,7 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
 
 stokes_status stokes_apply(stokes_ctx* c, int op, const double* in, double* out) {
     if (!c || !out || op < 0 || op > STOKES_OP_MG_A) return STOKES_E_ARG;
+    if (c->nbatch > 1) return STOKES_E_STATE;
     ST_TRY(apply_impl(c, op, in, out, hipMemcpyHostToDevice, hipMemcpyDeviceToHost));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return STOKES_OK;
@@ -1751,6 +2086,7 @@ stokes_status stokes_apply(stokes_ctx* c, int op, const double* in, double* out)
 
 stokes_status stokes_apply_device(stokes_ctx* c, int op, const double* in, double* out) {
     if (!c || !out || op < 0 || op > STOKES_OP_MG_A) return STOKES_E_ARG;
+    if (c->nbatch > 1) return STOKES_E_STATE;
     return apply_impl(c, op, in, out, hipMemcpyDeviceToDevice, hipMemcpyDeviceToDevice);
 }
 
@@ -1762,6 +2098,7 @@ stokes_status stokes_apply_device(stokes_ctx* c, int op, const double* in, doubl
 // stream: no allocation, no memset, no synchronisation.
 stokes_status stokes_apply_device_noalloc(stokes_ctx* c, int op, const double* in, double* out) {
     if (!c || !out) return STOKES_E_ARG;
+    if (c->nbatch > 1) return STOKES_E_STATE;
     if (op != STOKES_OP_A && op != STOKES_OP_B && op != STOKES_OP_BT && op != STOKES_OP_SHAT &&
         op != STOKES_OP_DIAG_A && op != STOKES_OP_DIAG_SHAT && op != STOKES_OP_PROJECT)
         return STOKES_E_ARG;

@@ -33,6 +33,7 @@ EXPORTED = [
     "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
     "stokes_destroy", "stokes_status_str", "stokes_preprocess", "stokes_setup_on_stream",
     "stokes_estimate_bytes", "stokes_apply_device_noalloc", "stokes_setup_with_allocator",
+    "stokes_setup_batch", "stokes_batch_result",
 ]
 EXPORTED_SERVER = [
     "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
@@ -156,6 +157,8 @@ def load():
         "stokes_setup_on_stream": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint, vp], ip),
         "stokes_setup_with_allocator": ([ctypes.POINTER(vp), vp, ip, dp, ctypes.c_uint, vp,
                                          ctypes.POINTER(StokesAllocator)], ip),
+        "stokes_setup_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ip, ip, dp, ctypes.c_uint, vp], ip),
+        "stokes_batch_result": ([vp, ip, ctypes.POINTER(StokesReport), vp, vp], ip),
         "stokes_estimate_bytes": ([ip, ctypes.c_uint, ip, i64p], ip),
         "stokes_server_create": ([ctypes.POINTER(vp), ip, ctypes.c_int64], ip),
         "stokes_server_submit": ([vp, vp, ip, dp, ip, ctypes.c_double, ip, i64p], ip),
@@ -438,6 +441,76 @@ def stokes_setup_on_stream(mask, N, force, flags, stream):
     _check(load().stokes_setup_on_stream(ctypes.byref(ctx), mask.ctypes.data, int(N), f, ctypes.c_uint(flags),
                                          ctypes.c_void_p(stream)), "stokes_setup_on_stream")
     return ctx
+
+
+class StokesBatch:
+    """Several geometries of one size solved together (stokes_setup_batch):
+    every kernel launch advances all members; mixed precision.  masks: a list
+    of uint8 (N, N, N) arrays indexed [k][j][i], 1 = fluid."""
+
+    def __init__(self, masks, force=(1.0, 0.0, 0.0), keep_all=False, stream=None, **options):
+        arrs = [np.ascontiguousarray(m, dtype=np.uint8) for m in masks]
+        if not arrs:
+            raise ValueError("a batch needs at least one mask")
+        self.N = int(arrs[0].shape[0])
+        if any(a.shape != (self.N,) * 3 for a in arrs):
+            raise ValueError("all members need the same N^3 shape")
+        self.size = len(arrs)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        ptrs = (ctypes.c_void_p * self.size)(*[a.ctypes.data for a in arrs])
+        f = np.ascontiguousarray(force, dtype=np.float64)
+        self._ctx = ctypes.c_void_p()
+        _check(load().stokes_setup_batch(ctypes.byref(self._ctx), ptrs, self.size, self.N,
+                                         f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.c_uint(STOKES_KEEP_ALL_COMPONENTS if keep_all else 0),
+                                         ctypes.c_void_p(stream)), "stokes_setup_batch")
+        for k, v in options.items():
+            stokes_set_option(self._ctx, k, v)
+
+    def set_option(self, key, value):
+        stokes_set_option(self._ctx, key, value)
+
+    def solve(self, precond=STOKES_SIMPLE, tol=1e-8):
+        """Solves every member; returns the list of their reports."""
+        if isinstance(precond, str):
+            precond = {"uzawa": STOKES_UZAWA, "simple": STOKES_SIMPLE}[precond.lower()]
+        rep = StokesReport()
+        load().stokes_solve(self._ctx, int(precond), float(tol), ctypes.byref(rep))
+        return [self.result(m)[0] for m in range(self.size)]
+
+    def result(self, member, fields=False):
+        """(report, p, u) of one member; p and u only with fields=True."""
+        rep = StokesReport()
+        N = self.N
+        p = np.zeros(N ** 3) if fields else None
+        u = np.zeros(3 * N ** 3) if fields else None
+        _check(load().stokes_batch_result(self._ctx, int(member), ctypes.byref(rep),
+                                          p.ctypes.data if fields else None, u.ctypes.data if fields else None),
+               "stokes_batch_result")
+        if fields:
+            return rep.to_dict(), p.reshape(N, N, N), u.reshape(3, N, N, N)
+        return rep.to_dict(), None, None
+
+    def info(self):
+        return stokes_info(self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            stokes_destroy(self._ctx)
+            self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 SERVER_STATS = ["submitted", "completed", "queued", "running", "bytes_in_use", "peak_bytes", "peak_running",
