@@ -34,7 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SERVE_SLOTS = 8
+SERVE_SLOTS = 4              # the box's hardware queues (GPU_MAX_HW_QUEUES default)
 SERVE_BUDGET = 8 << 30          # HBM budget of the request server (bytes)
 
 # name: (description, side, generator)
@@ -321,17 +321,19 @@ def collect(srv, ids, phase):
     return res
 
 
-def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345):
+def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345, max_members=32):
     """Saturated throughput from the whole request stream submitted at once,
     then the same stream with Poisson arrivals at frac of that rate; latency =
-    result ready - submitted."""
+    result ready - submitted.  max_members: requests per batched context (1:
+    every request on a context of its own)."""
     import numpy as np
 
-    with P.Server(slots, budget) as srv:
+    with P.Server(slots, budget, max_members=max_members) as srv:
         t0 = srv.clock()
         ids = [srv.submit(m, precision=1) for _, m in reqs]
         res = collect(srv, ids, "saturated")
         mu = len(reqs) / (max(r["t_end"] for r in res) - t0)
+        sat_stats = srv.stats()
         log(f"[serve] saturated: {len(reqs)} requests in {len(reqs) / mu:.2f} s -> {mu:.2f} requests/s")
         rate = frac * mu
         gaps = np.random.default_rng(seed).exponential(1.0 / rate, len(reqs))
@@ -354,13 +356,18 @@ def serve(P, reqs, slots=SERVE_SLOTS, budget=SERVE_BUDGET, frac=0.8, seed=12345)
     return {
         "requests": len(reqs), "slots": slots, "hbm_budget_GB": budget / 2 ** 30,
         "precision": "mixed", "precond": "simple", "tol": 1e-8,
-        "saturated_requests_per_s": mu, "arrival_rate_per_s": rate, "arrival_frac": frac,
+        "saturated_requests_per_s": mu, "saturated_voxels_per_s": mu * sum(p["N"] ** 3 for p, _ in reqs) / len(reqs),
+        "arrival_rate_per_s": rate, "arrival_frac": frac,
         "throughput_requests_per_s": len(reqs) / span,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "mean": float(lat.mean() * 1e3), "max": float(lat.max() * 1e3)},
         "queue_wait_ms_p50": float(np.percentile([r["t_start"] - r["t_submit"] for r in res], 50) * 1e3),
         "peak_running": stats["peak_running"], "peak_bytes_GB": stats["peak_bytes"] / 2 ** 30,
         "voxels_per_s": cells / span, "failed": len(bad),
+        "max_members_per_context": max_members,
+        "saturated_requests_per_context": sat_stats["requests_on_contexts"] / max(1, sat_stats["contexts"]),
+        "poisson_requests_per_context": (stats["requests_on_contexts"] - sat_stats["requests_on_contexts"]) /
+                                        max(1, stats["contexts"] - sat_stats["contexts"]),
         "workload": "seeded request stream: spheres r 2..6 or GRF corr length 4..12 (50/50), N in "
                     "{32,48,64,96,128}, porosity 0.15..0.6, force x",
     }
@@ -393,6 +400,8 @@ def main():
                     help="serving requests run beside the solve benchmark (0 = skip)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
+    ap.add_argument("--serve-members", type=int, default=32,
+                    help="requests per batched context in the server (1 = no batching)")
     ap.add_argument("--study", choices=["precond"],
                     help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries")
     args = ap.parse_args()
@@ -419,7 +428,7 @@ def main():
         precond_study(P)
         return
     if args.serve_only:
-        sv = serve(P, reqs, slots=args.serve_slots)
+        sv = serve(P, reqs, slots=args.serve_slots, max_members=args.serve_members)
         out = {"metric": "permeability solves/s (serving)", "value": sv["throughput_requests_per_s"],
                "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
                "dtype": "f32+f64", "data": "synthetic", "config": {"workload": sv["workload"]}, "serving": sv}
@@ -569,7 +578,7 @@ def main():
     if not args.no_large and args.workload != "grf512":
         out["large_mixed_solve"] = large_solve(P, torch)
     if reqs:
-        out["serving"] = serve(P, reqs, slots=args.serve_slots)
+        out["serving"] = serve(P, reqs, slots=args.serve_slots, max_members=args.serve_members)
         log(f"[serve] {out['serving']['throughput_requests_per_s']:.2f} requests/s, latency p50 "
             f"{out['serving']['latency_ms']['p50']:.0f} ms p99 {out['serving']['latency_ms']['p99']:.0f} ms")
     if not args.no_cpu_baseline and N <= 256:

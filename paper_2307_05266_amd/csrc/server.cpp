@@ -6,14 +6,18 @@
 // the queue as soon as a slot is free and the request's device bytes (bounded
 // by stokes_estimate_bytes) fit in what the HBM budget has left; a request
 // that arrives while others run is admitted the moment a slot and memory free
-// up, and its kernels overlap with theirs on the device (each slot's stream
-// maps onto its own hardware queue when enough are configured).  Each request
-// gets its own context (stokes_setup_on_stream: stream-ordered allocation, so
-// setting up or tearing down one request never waits for the others); its
-// Krylov state stays resident in that context for the whole solve, and its
-// inner iterations replay captured HIP graphs.  The solve of a request is the
-// same sequence of kernels with the same deterministic reductions whether it
-// runs alone or among others, so its result is bitwise the same.
+// up, and its kernels overlap with theirs on the device.  A slot that takes a
+// mixed-precision request also takes the queued requests that can share its
+// context (same box size, force, preconditioner and tolerance, as many as
+// the member and cell caps and the budget allow, in queue order) and solves
+// them as one batched context (stokes_setup_batch): every kernel launch then
+// advances all of them, which amortises the per-launch latency that bounds
+// small solves.  FP64 requests get a context each (stokes_setup_on_stream).
+// Each context allocates in its stream's order, so setting up or tearing down
+// one never waits for the others; its Krylov state stays resident for the
+// whole solve, and its inner iterations replay captured HIP graphs.  A
+// request's arithmetic does not depend on its batch or on the other work on
+// the device, so its result is bitwise the same alone or in the mix.
 //
 // Only the public C-ABI of the solver is used here.
 
@@ -44,6 +48,7 @@ struct Request {
     double tol = 1e-8;
     int precision = 0;
     int64_t bytes = 0;        // admission charge
+    bool valid = true;        // mask bytes are 0 or 1
     bool done = false;
     stokes_request_result res{};
 };
@@ -54,6 +59,8 @@ struct stokes_server {
     int device = 0;
     int slots = 1;
     int64_t budget = 0;
+    int max_members = 32;             // requests sharing one batched context
+    int64_t max_cells = int64_t(1) << 21;   // voxels of one batched context (members x N^3)
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -65,6 +72,7 @@ struct stokes_server {
     int64_t in_use = 0, peak = 0;
     int64_t submitted = 0, completed = 0;
     int running = 0, peak_running = 0;
+    int64_t batches = 0, batched_requests = 0;
     bool stop = false;
     std::vector<std::thread> workers;
 
@@ -75,7 +83,18 @@ struct stokes_server {
 
 namespace {
 
-void run_request(stokes_server* srv, Request* r, hipStream_t stream) {
+void fill_result(stokes_request_result& o, stokes_status st, const stokes_report& rep) {
+    o.status = st;
+    o.k_hat = rep.k_hat;
+    o.outer_iters = rep.outer_iters;
+    o.inner_A_iters = rep.inner_A_iters;
+    o.inner_S_iters = rep.inner_S_iters;
+    o.rel_res = rep.rel_res;
+    o.div_norm = rep.div_norm;
+}
+
+// One FP64 request on a context of its own.
+void run_single(stokes_server* srv, Request* r, hipStream_t stream) {
     stokes_request_result& o = r->res;
     stokes_ctx* ctx = nullptr;
     stokes_status st = stokes_setup_on_stream(&ctx, r->mask.data(), r->N, r->force, 0u, stream);
@@ -87,24 +106,65 @@ void run_request(stokes_server* srv, Request* r, hipStream_t stream) {
         if (stokes_info(ctx, info) == STOKES_OK) o.device_bytes = info[9];
         stokes_destroy(ctx);
     }
-    o.status = st;
-    o.k_hat = rep.k_hat;
-    o.outer_iters = rep.outer_iters;
-    o.inner_A_iters = rep.inner_A_iters;
-    o.inner_S_iters = rep.inner_S_iters;
-    o.rel_res = rep.rel_res;
-    o.div_norm = rep.div_norm;
+    fill_result(o, st, rep);
     o.t_end = srv->now();
-    r->mask.clear();
-    r->mask.shrink_to_fit();
+}
+
+// Mixed-precision requests of one size, force, preconditioner and tolerance
+// on one batched context.  When the batch cannot be set up as a whole, each
+// request runs as a batch of its own, so one request's error stays its own.
+void run_batch(stokes_server* srv, const std::vector<Request*>& b, hipStream_t stream) {
+    const int B = (int)b.size();
+    std::vector<const uint8_t*> masks(B);
+    for (int m = 0; m < B; ++m) masks[m] = b[m]->mask.data();
+    stokes_ctx* ctx = nullptr;
+    stokes_status st = stokes_setup_batch(&ctx, masks.data(), B, b[0]->N, b[0]->force, 0u, stream);
+    if (st != STOKES_OK && B > 1) {
+        for (Request* r : b) run_batch(srv, std::vector<Request*>{r}, stream);
+        return;
+    }
+    stokes_report rep{};
+    stokes_status solved = st;
+    if (st == STOKES_OK) solved = stokes_solve(ctx, b[0]->precond, b[0]->tol, &rep);
+    int64_t info[12] = {};
+    if (ctx && stokes_info(ctx, info) != STOKES_OK) info[9] = 0;
+    const double t = srv->now();
+    for (int m = 0; m < B; ++m) {
+        stokes_request_result& o = b[m]->res;
+        stokes_report mr{};
+        stokes_status ms = st;
+        if (st == STOKES_OK) {
+            ms = stokes_batch_result(ctx, m, &mr, nullptr, nullptr);
+            if (ms == STOKES_OK) ms = (stokes_status)mr.status;
+            else ms = solved;
+        }
+        fill_result(o, ms, mr);
+        o.device_bytes = info[9] / B;
+        o.t_end = t;
+    }
+    if (ctx) stokes_destroy(ctx);
+}
+
+bool mask_valid(const Request* r) {
+    for (uint8_t v : r->mask)
+        if (v > 1) return false;
+    return true;
+}
+
+bool can_share(const Request* a, const Request* b) {
+    return a->precision == 1 && b->precision == 1 && a->N == b->N && a->precond == b->precond &&
+           a->tol == b->tol && a->force[0] == b->force[0] && a->force[1] == b->force[1] &&
+           a->force[2] == b->force[2] && b->valid;
 }
 
 void worker(stokes_server* srv) {
     (void)hipSetDevice(srv->device);
     hipStream_t stream = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    std::vector<Request*> batch;
     for (;;) {
-        Request* r = nullptr;
+        int64_t charge = 0;
+        batch.clear();
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             srv->work_cv.wait(lk, [srv] {
@@ -112,26 +172,56 @@ void worker(stokes_server* srv) {
                        (!srv->queue.empty() && srv->in_use + srv->queue.front()->bytes <= srv->budget);
             });
             if (srv->stop) break;
-            r = srv->queue.front();
+            Request* head = srv->queue.front();
             srv->queue.pop_front();
-            r->res.t_start = srv->now();
-            srv->in_use += r->bytes;
+            batch.push_back(head);
+            charge = head->bytes;
+            if (head->precision == 1 && head->valid) {
+                const int64_t n3 = (int64_t)head->N * head->N * head->N;
+                const int64_t cap = std::min<int64_t>(srv->max_members, std::max<int64_t>(1, srv->max_cells / n3));
+                for (auto it = srv->queue.begin(); it != srv->queue.end() && (int64_t)batch.size() < cap;) {
+                    Request* r = *it;
+                    if (can_share(head, r) && srv->in_use + charge + r->bytes <= srv->budget) {
+                        batch.push_back(r);
+                        charge += r->bytes;
+                        it = srv->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            const double t = srv->now();
+            for (Request* r : batch) {
+                r->res.t_start = t;
+                r->res.batch_members = (int)batch.size();
+            }
+            srv->in_use += charge;
             srv->peak = std::max(srv->peak, srv->in_use);
-            ++srv->running;
+            srv->running += (int)batch.size();
             srv->peak_running = std::max(srv->peak_running, srv->running);
+            ++srv->batches;
+            srv->batched_requests += (int64_t)batch.size();
         }
-        if (have_stream) {
-            run_request(srv, r, stream);
+        if (!have_stream) {
+            for (Request* r : batch) {
+                r->res.status = STOKES_E_DEVICE;
+                r->res.t_end = srv->now();
+            }
+        } else if (batch[0]->precision == 1 && batch[0]->valid) {
+            run_batch(srv, batch, stream);
         } else {
-            r->res.status = STOKES_E_DEVICE;
-            r->res.t_end = srv->now();
+            run_single(srv, batch[0], stream);
+        }
+        for (Request* r : batch) {
+            r->mask.clear();
+            r->mask.shrink_to_fit();
         }
         {
             std::lock_guard<std::mutex> lk(srv->mu);
-            srv->in_use -= r->bytes;
-            --srv->running;
-            ++srv->completed;
-            r->done = true;
+            srv->in_use -= charge;
+            srv->running -= (int)batch.size();
+            srv->completed += (int64_t)batch.size();
+            for (Request* r : batch) r->done = true;
         }
         srv->work_cv.notify_all();
         srv->done_cv.notify_all();
@@ -187,6 +277,7 @@ stokes_status stokes_server_submit(stokes_server* srv, const uint8_t* mask, int 
         return STOKES_E_NOMEM;
     }
     r->N = N;
+    r->valid = mask_valid(r.get());
     std::memcpy(r->force, force, sizeof(r->force));
     r->precond = precond;
     r->tol = tol;
@@ -219,7 +310,15 @@ stokes_status stokes_server_wait(stokes_server* srv, int64_t id, stokes_request_
     return STOKES_OK;
 }
 
-stokes_status stokes_server_stats(stokes_server* srv, int64_t stats[8]) {
+stokes_status stokes_server_set_batching(stokes_server* srv, int max_members, int64_t max_cells) {
+    if (!srv || max_members < 1 || max_members > 32 || max_cells < 1) return STOKES_E_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->max_members = max_members;
+    srv->max_cells = max_cells;
+    return STOKES_OK;
+}
+
+stokes_status stokes_server_stats(stokes_server* srv, int64_t stats[10]) {
     if (!srv || !stats) return STOKES_E_ARG;
     std::lock_guard<std::mutex> lk(srv->mu);
     stats[0] = srv->submitted;
@@ -230,6 +329,8 @@ stokes_status stokes_server_stats(stokes_server* srv, int64_t stats[8]) {
     stats[5] = srv->peak;
     stats[6] = srv->peak_running;
     stats[7] = srv->budget;
+    stats[8] = srv->batches;
+    stats[9] = srv->batched_requests;
     return STOKES_OK;
 }
 

@@ -1240,7 +1240,7 @@ static stokes_status setup_common(stokes_ctx** out, const uint8_t* const* masks,
         int64_t est = 0;
         st = stokes_estimate_bytes(N, flags, 1, &est);
         if (st == STOKES_OK) {
-            c->bstride = ((size_t)est + (size_t)(64 << 10) + 4095) & ~(size_t)4095;
+            c->bstride = (size_t)est;
             char* slab = nullptr;
             st = dev_alloc(c, &slab, c->bstride * (size_t)B);
             c->slab = slab;
@@ -1321,7 +1321,11 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
         }
     }
     if (precision == 1) t += 4 * blk(3 * n3, 4) + 5 * blk(n3, 4);
-    *bytes = t;
+    // 256-byte alignment of every buffer inside a batched context's member
+    // part (fewer than 256 buffers), rounded to whole 4 KiB pages: a member's
+    // part of a batched context is exactly this many bytes
+    t += 256 * 256;
+    *bytes = (t + 4095) / 4096 * 4096;
     return STOKES_OK;
 }
 

@@ -37,7 +37,7 @@ EXPORTED = [
 ]
 EXPORTED_SERVER = [
     "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
-    "stokes_server_clock", "stokes_server_destroy",
+    "stokes_server_clock", "stokes_server_destroy", "stokes_server_set_batching",
 ]
 
 
@@ -68,6 +68,7 @@ class StokesRequestResult(ctypes.Structure):
         ("outer_iters", ctypes.c_int), ("inner_A_iters", ctypes.c_int), ("inner_S_iters", ctypes.c_int),
         ("rel_res", ctypes.c_double), ("div_norm", ctypes.c_double), ("device_bytes", ctypes.c_int64),
         ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+        ("batch_members", ctypes.c_int),
     ]
 
     def to_dict(self):
@@ -164,6 +165,7 @@ def load():
         "stokes_server_submit": ([vp, vp, ip, dp, ip, ctypes.c_double, ip, i64p], ip),
         "stokes_server_wait": ([vp, ctypes.c_int64, ctypes.POINTER(StokesRequestResult)], ip),
         "stokes_server_stats": ([vp, i64p], ip),
+        "stokes_server_set_batching": ([vp, ip, ctypes.c_int64], ip),
         "stokes_server_clock": ([vp], ctypes.c_double),
         "stokes_server_destroy": ([vp], None),
     }
@@ -514,18 +516,24 @@ class StokesBatch:
 
 
 SERVER_STATS = ["submitted", "completed", "queued", "running", "bytes_in_use", "peak_bytes", "peak_running",
-                "budget"]
+                "budget", "contexts", "requests_on_contexts"]
 
 
 class Server:
     """Request server (include/stokes_server.h): `slots` workers, each with its
     own stream, admit queued solves as slots and HBM budget free up."""
 
-    def __init__(self, slots, hbm_budget_bytes):
+    def __init__(self, slots, hbm_budget_bytes, max_members=None, max_cells=None):
         lib = load()
         self._srv = ctypes.c_void_p()
         _check(lib.stokes_server_create(ctypes.byref(self._srv), int(slots), ctypes.c_int64(int(hbm_budget_bytes))),
                "stokes_server_create")
+        if max_members is not None or max_cells is not None:
+            self.set_batching(32 if max_members is None else max_members, 1 << 21 if max_cells is None else max_cells)
+
+    def set_batching(self, max_members, max_cells=1 << 21):
+        _check(load().stokes_server_set_batching(self._srv, int(max_members), ctypes.c_int64(int(max_cells))),
+               "stokes_server_set_batching")
 
     def submit(self, mask, force=(1.0, 0.0, 0.0), precond=STOKES_SIMPLE, tol=1e-8, precision=1):
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
@@ -542,7 +550,7 @@ class Server:
         return out.to_dict()
 
     def stats(self):
-        st = (ctypes.c_int64 * 8)()
+        st = (ctypes.c_int64 * 10)()
         _check(load().stokes_server_stats(self._srv, st), "stokes_server_stats")
         return {k: int(st[i]) for i, k in enumerate(SERVER_STATS)}
 

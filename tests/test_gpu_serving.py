@@ -1,9 +1,11 @@
 """GPU tests of the request server (continuous batching of solves).
 
 The bar: a request's result in the mix is bitwise the result of the same
-solve run alone through the plain context API; admission never lets the
-contexts of running requests exceed the HBM budget; requests overlap on the
-device when the budget allows it; errors are reported per request.
+solve run alone through the context API (a one-member batched context for
+mixed precision, a plain context for FP64); requests of one size that wait
+together share one batched context; admission never lets the contexts of
+running requests exceed the HBM budget; requests overlap on the device when
+the budget allows it; errors are reported per request.
 """
 
 import sys
@@ -50,8 +52,9 @@ def test_estimate_bounds_what_a_context_holds(P):
             held32 = s.info()["device_bytes"]
         e64, e32 = P.stokes_estimate_bytes(N, 0), P.stokes_estimate_bytes(N, 1)
         say(f"    N={N}: fp64 held {held64} est {e64}; mixed held {held32} est {e32}")
-        # slack: component arrays at their limit (2048) and the label array
-        slack = 256 * 2048 * 8 + 2 * 2048 * 8 + 2 * N ** 3
+        # slack: component arrays at their limit (2048), the label array, the
+        # alignment allowance of a batched member's part, whole pages
+        slack = 256 * 2048 * 8 + 2 * 2048 * 8 + 2 * N ** 3 + 256 * 256 + 4096
         assert held64 <= e64 <= held64 + slack
         assert held32 <= e32 <= held32 + slack
 
@@ -60,8 +63,12 @@ def test_result_alone_equals_result_in_the_mix(P):
     reqs = requests_mix()
     alone = []
     for m, f, pc, prec in reqs:
-        with P.Stokes(m, f, precision=prec) as s:
-            alone.append(s.solve(pc, 1e-8))
+        if prec == 1:
+            with P.StokesBatch([m], f) as b:
+                alone.append(b.solve(pc, 1e-8)[0])
+        else:
+            with P.Stokes(m, f, precision=prec) as s:
+                alone.append(s.solve(pc, 1e-8))
     budget = 4 * max(P.stokes_estimate_bytes(m.shape[0], prec) for m, _, _, prec in reqs)
     with P.Server(4, budget) as srv:
         # filler requests before and after, so every request shares the device
@@ -82,6 +89,38 @@ def test_result_alone_equals_result_in_the_mix(P):
         assert (r["outer_iters"], r["inner_A_iters"], r["inner_S_iters"]) == \
             (a["outer_iters"], a["inner_A_iters"], a["inner_S_iters"])
         assert r["div_norm"] == a["div_norm"]
+
+
+def test_waiting_requests_of_one_size_share_a_batched_context(P):
+    """One slot, held by a larger FP64 request while ten 32^3 mixed requests queue
+    up: they then run as one batched context, each bitwise as alone."""
+    small = [spheres(32, 3.0, 0.45, 500 + q) if q % 2 else grf(32, 4.0, 0.35, 500 + q) for q in range(10)]
+    alone = []
+    for m in small:
+        with P.StokesBatch([m]) as b:
+            alone.append(b.solve(P.STOKES_SIMPLE, 1e-8)[0])
+    budget = P.stokes_estimate_bytes(64, 0) + 10 * P.stokes_estimate_bytes(32, 1)
+    with P.Server(1, budget) as srv:
+        first = srv.submit(spheres(64, 3.0, 0.5, 499), precision=0)
+        ids = [srv.submit(m, precision=1) for m in small]
+        r0 = srv.wait(first)
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    say(f"    {st}; members per context: {[r['batch_members'] for r in res]}")
+    assert r0["status"] == 0 and r0["batch_members"] == 1
+    assert st["contexts"] == 2 and st["requests_on_contexts"] == 11
+    for a, r in zip(alone, res):
+        assert r["status"] == 0 and r["batch_members"] == 10
+        assert r["k_hat"] == a["k_hat"] and r["div_norm"] == a["div_norm"]
+        assert (r["outer_iters"], r["inner_A_iters"], r["inner_S_iters"]) == \
+            (a["outer_iters"], a["inner_A_iters"], a["inner_S_iters"])
+        assert r["device_bytes"] == P.stokes_estimate_bytes(32, 1)
+    # without batching each request gets a context of its own, with the same results
+    with P.Server(1, budget, max_members=1) as srv:
+        ids = [srv.submit(m, precision=1) for m in small[:3]]
+        res1 = [srv.wait(i) for i in ids]
+    for a, r in zip(alone, res1):
+        assert r["batch_members"] == 1 and r["k_hat"] == a["k_hat"]
 
 
 def test_admission_respects_the_budget_and_overlaps(P):
