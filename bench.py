@@ -112,6 +112,30 @@ def precond_study(P):
         print(json.dumps(row), flush=True)
 
 
+def batch_study(P, torch, members=(1, 4, 8, 16, 32), sides=(32, 48, 64)):
+    """Mixed-precision SIMPLE solves of small boxes (spheres r=3, porosity 0.45):
+    one batched context of B members against B contexts of one member solved
+    one after another, time per request; one JSON line per size."""
+    from synth import spheres
+    for N in sides:
+        row = {"study": "batch", "N": N, "workload": f"{N}^3 spheres r=3 porosity 0.45, mixed SIMPLE, tol 1e-8"}
+        for B in members:
+            if B * N ** 3 > (1 << 21) and B > 1:
+                continue
+            masks = [spheres(N, 3.0, 0.45, 7000 + q) for q in range(B)]
+            with P.StokesBatch(masks) as b:
+                b.solve("simple", 1e-8)                  # graphs captured, caches warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = b.solve("simple", 1e-8)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            row[f"batch_{B}_ms_per_request"] = dt / B * 1e3
+            row[f"batch_{B}_outer_mean"] = sum(r["outer_iters"] for r in reps) / B
+            log(f"[batch study] N={N} B={B}: {dt * 1e3:.1f} ms, {dt / B * 1e3:.2f} ms per request")
+        print(json.dumps(row), flush=True)
+
+
 def measured_traffic(kernel, N):
     """HBM bytes per launch of `kernel` from the committed hardware-counter summary,
     or None when that summary was taken at another size or on other kernel code
@@ -402,8 +426,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
     ap.add_argument("--serve-members", type=int, default=32,
                     help="requests per batched context in the server (1 = no batching)")
-    ap.add_argument("--study", choices=["precond"],
-                    help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries")
+    ap.add_argument("--study", choices=["precond", "batch"],
+                    help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries (precond), or "
+                         "batched contexts against one context per request for small boxes (batch)")
     args = ap.parse_args()
     if args.oracle_counts:
         measure_oracle_counts(args.workload)
@@ -426,6 +451,9 @@ def main():
     P.load()
     if args.study == "precond":
         precond_study(P)
+        return
+    if args.study == "batch":
+        batch_study(P, torch)
         return
     if args.serve_only:
         sv = serve(P, reqs, slots=args.serve_slots, max_members=args.serve_members)
