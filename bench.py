@@ -85,11 +85,11 @@ def stream_copy_gbps(torch, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def precond_study(P):
+def precond_study(P, cases=None):
     """One JSON line per geometry: outer iterations, inner iterations and solve
     time of the FP64 solve (tol 1e-8) with each preconditioner."""
     import torch
-    for desc, gen in PRECOND_STUDY:
+    for desc, gen in (cases or PRECOND_STUDY):
         mask = gen()
         with P.Stokes(mask, (1.0, 0.0, 0.0)) as s:
             s.set_option("progress", 250)              # Uzawa may take thousands of outer iterations
@@ -426,7 +426,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
     ap.add_argument("--serve-members", type=int, default=32,
                     help="requests per batched context in the server (1 = no batching)")
-    ap.add_argument("--study", choices=["precond", "batch"],
+    ap.add_argument("--study", choices=["precond", "precond256", "batch"],
                     help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries (precond), or "
                          "batched contexts against one context per request for small boxes (batch)")
     args = ap.parse_args()
@@ -451,6 +451,10 @@ def main():
     P.load()
     if args.study == "precond":
         precond_study(P)
+        return
+    if args.study == "precond256":
+        # the 256^3 tight pack: SIMPLE (the headline solve) against Uzawa
+        precond_study(P, [(WORKLOADS["tight256"][0], WORKLOADS["tight256"][2])])
         return
     if args.study == "batch":
         batch_study(P, torch)

@@ -71,15 +71,28 @@ struct MemberScalars {
     double v[kMaxBatch];
 };
 
+// Pointer arithmetic on the pointer itself (not through an integer), so the
+// compiler still knows what it points into (its no-alias facts survive); a
+// null pointer stays null.
 template <class P>
 __device__ __forceinline__ void shift1(P& p, size_t o) {
-    if (p) p = reinterpret_cast<P>(reinterpret_cast<uintptr_t>(p) + o);
+    p = (P)(const_cast<char*>(reinterpret_cast<const char*>(p)) + (p ? o : (size_t)0));
 }
 
 // Point each pointer at this block's member (grid y) of a batched context.
 template <class... P>
 __device__ __forceinline__ void shift_all(size_t o, P&... p) {
     (shift1(p, o), ...);
+}
+
+// The same for pointers that are never null (no select on the offset).
+template <class P>
+__device__ __forceinline__ void shift1_nn(P& p, size_t o) {
+    p = (P)(const_cast<char*>(reinterpret_cast<const char*>(p)) + o);
+}
+template <class... P>
+__device__ __forceinline__ void shift_nn(size_t o, P&... p) {
+    (shift1_nn(p, o), ...);
 }
 
 // Outer-loop kernels skip the members that sit out the current step.
@@ -233,7 +246,7 @@ __device__ __forceinline__ int fluid_bit(const uint32_t* bits, int N, int wpr, i
 }
 
 __global__ void k_face_codes(Sweep s, const uint32_t* __restrict__ bits, int wpr, uint8_t* __restrict__ code) {
-    shift_all((size_t)blockIdx.y * s.bstride, bits, code);
+    shift_nn((size_t)blockIdx.y * s.bstride, bits, code);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     const int N = s.N;
@@ -269,7 +282,7 @@ __device__ __forceinline__ double diag_Shat_cell(const uint8_t* __restrict__ cod
 }
 
 __global__ void k_inv_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ inv) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, inv);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, inv);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -290,7 +303,7 @@ __device__ __forceinline__ double apply_A_face(const double* __restrict__ u, con
 
 __global__ void k_apply_A(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ u,
                           double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, u, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, u, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -306,7 +319,7 @@ __global__ void k_apply_A(Sweep s, const uint8_t* __restrict__ code, const doubl
 // (B^T p)(c, X) = p_X - p_{X - e_c} on active faces
 __global__ void k_apply_BT(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p,
                            double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, p, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -326,7 +339,7 @@ __global__ void k_apply_BT(Sweep s, const uint8_t* __restrict__ code, const doub
 // f - B^T p on active faces (right-hand side of the velocity recovery)
 __global__ void k_force_minus_BT(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p, double f0,
                                  double f1, double f2, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, p, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -345,7 +358,7 @@ __global__ void k_force_minus_BT(Sweep s, const uint8_t* __restrict__ code, cons
 
 // (B u)_X = sum_c [u(c, X) - u(c, X + e_c)]  (0 in solid cells by the invariant)
 __global__ void k_apply_B(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, u, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -372,7 +385,7 @@ __device__ __forceinline__ double apply_Shat_cell(const double pX, const double 
 
 __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ p,
                              double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, p, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, p, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -382,7 +395,7 @@ __global__ void k_apply_Shat(Sweep s, const uint8_t* __restrict__ code, const do
 }
 
 __global__ void k_diag_A(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -394,7 +407,7 @@ __global__ void k_diag_A(Sweep s, const uint8_t* __restrict__ code, double* __re
 }
 
 __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -405,7 +418,7 @@ __global__ void k_diag_Shat(Sweep s, const uint8_t* __restrict__ code, double* _
 
 // zero the entries that are not unknowns (inactive faces / solid cells)
 __global__ void k_mask_faces(Sweep s, const uint8_t* __restrict__ code, double* __restrict__ u) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, u);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, u);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -418,7 +431,7 @@ __global__ void k_mask_faces(Sweep s, const uint8_t* __restrict__ code, double* 
 }
 
 __global__ void k_mask_cells(Sweep s, const uint32_t* __restrict__ bits, int wpr, double* __restrict__ p) {
-    shift_all((size_t)blockIdx.y * s.bstride, bits, p);
+    shift_nn((size_t)blockIdx.y * s.bstride, bits, p);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -554,7 +567,8 @@ __device__ __forceinline__ void face_tab_fill(FaceTab<T>& t) {
 template <class T>
 __global__ void k_cgA_init(Sweep s, const uint8_t* __restrict__ code, const double* b, double f0, double f1,
                            double f2, T* __restrict__ x, T* r, CgState* st, double* part, double eps, int maxit) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, b, x, r, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, x, r, st, part);
+    shift_all((size_t)blockIdx.y * s.bstride, b);
     if (!member_active(s.active)) {
         // this member sits the solve out: it is done before its first iteration
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -603,7 +617,8 @@ __device__ __forceinline__ int s_of(int code, int a) { return a == 0 ? sx_of(cod
 template <class T>
 __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __restrict__ r, T* __restrict__ d,
                           CgState* st, double* part, const T* __restrict__ zpre) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, r, d, st, part, zpre);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, r, d, st, part);
+    shift_all((size_t)blockIdx.y * s.bstride, zpre);
     if (st->done) return;
     double beta_d;
     int j;
@@ -647,7 +662,7 @@ __global__ void k_cgA_dir(Sweep s, const uint8_t* __restrict__ code, const T* __
 template <class T>
 __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __restrict__ x, T* __restrict__ r,
                              const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, x, r, d, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, x, r, d, q, st, part);
     if (st->done) return;
     double alpha_d;
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
@@ -700,7 +715,7 @@ __global__ void k_cgA_update(Sweep s, const uint8_t* __restrict__ code, T* __res
 template <class T>
 __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b, T* __restrict__ x, T* r,
                            CgState* st, double* part, double eps, int maxit) {
-    shift_all((size_t)blockIdx.y * s.bstride, invd, b, x, r, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, invd, b, x, r, st, part);
     if (!member_active(s.active)) {
         // this member sits the solve out: it is done before its first iteration
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -739,7 +754,8 @@ __global__ void k_cgS_init(Sweep s, const T* __restrict__ invd, const double* b,
 template <class T>
 __global__ void k_cgS_dir(Sweep s, const T* __restrict__ invd, const T* __restrict__ r, T* __restrict__ d,
                           CgState* st, double* part, const T* __restrict__ zpre) {
-    shift_all((size_t)blockIdx.y * s.bstride, invd, r, d, st, part, zpre);
+    shift_nn((size_t)blockIdx.y * s.bstride, invd, r, d, st, part);
+    shift_all((size_t)blockIdx.y * s.bstride, zpre);
     if (st->done) return;
     double beta_d;
     int j;
@@ -827,7 +843,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_cgS_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
                                                               const T* __restrict__ d, T* __restrict__ q,
                                                               CgState* st, double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
     if (st->done) return;
     __shared__ T tl[2][kTileMax];
     __shared__ FaceTab<T> ft;
@@ -871,7 +887,7 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_cgA_stencil_tiled(Sweep s, const uint8_t* __restrict__ code,
                                                               const T* __restrict__ d, T* __restrict__ q,
                                                               CgState* st, double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, d, q, st, part);
     if (st->done) return;
     __shared__ T tl[2][3][kTileMax];
     __shared__ FaceTab<T> ft;
@@ -935,7 +951,7 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_tiled(Sweep s, const 
                                                                  const T* __restrict__ z, const T* __restrict__ din,
                                                                  T* __restrict__ dout, T* __restrict__ q, CgState* st,
                                                                  double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
     if (st->done) return;
     double beta_d;
     int j;
@@ -986,7 +1002,7 @@ __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const 
                                                                  const T* __restrict__ z, const T* __restrict__ din,
                                                                  T* __restrict__ dout, T* __restrict__ q, CgState* st,
                                                                  double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
     if (st->done) return;
     double beta_d;
     int j;
@@ -1049,7 +1065,7 @@ __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const 
 template <class T>
 __global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict__ x, T* __restrict__ r,
                              const T* __restrict__ d, const T* __restrict__ q, CgState* st, double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, invd, x, r, d, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, invd, x, r, d, q, st, part);
     if (st->done) return;
     double alpha_d;
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
@@ -1090,7 +1106,7 @@ __global__ void k_cgS_update(Sweep s, const T* __restrict__ invd, T* __restrict_
 // ---- mixed-precision helpers -------------------------------------------------
 // out = in converted to FP64 (cells)
 __global__ void k_widen_cells(Sweep s, const float* __restrict__ in, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, in, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, in, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -1101,7 +1117,7 @@ __global__ void k_widen_cells(Sweep s, const float* __restrict__ in, double* __r
 }
 
 __global__ void k_narrow_cells(Sweep s, const double* __restrict__ in, float* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, in, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, in, out);
     const Column c = sweep_column(s);
     if (!c.valid) return;
     for (int k = c.k0; k < c.k1; ++k) {
@@ -1114,7 +1130,7 @@ __global__ void k_narrow_cells(Sweep s, const double* __restrict__ in, float* __
 // partials of (res, res) and (rhs, rhs) to out[3*b + 0..1]
 __global__ void k_residual_A(Sweep s, const uint8_t* __restrict__ code, const double* __restrict__ rhs,
                              const double* __restrict__ u, double* __restrict__ res, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, rhs, u, res, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, rhs, u, res, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
@@ -1141,7 +1157,7 @@ __global__ void k_residual_A(Sweep s, const uint8_t* __restrict__ code, const do
 
 // u += a v with v in FP32 (faces)
 __global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* __restrict__ v, MemberScalars am) {
-    shift_all((size_t)blockIdx.y * s.bstride, u, v);
+    shift_nn((size_t)blockIdx.y * s.bstride, u, v);
     if (!member_active(s.active)) return;
     const double a = am.v[blockIdx.y];
     const Column c = sweep_column(s);
@@ -1154,7 +1170,7 @@ __global__ void k_axpy_faces_f32(Sweep s, double* __restrict__ u, const float* _
 
 // (B v)_X with v in FP32, result in FP64
 __global__ void k_apply_B_f32(Sweep s, const float* __restrict__ u, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, u, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -1174,7 +1190,8 @@ __global__ void k_apply_B_f32(Sweep s, const float* __restrict__ u, double* __re
 // up to three dot products of cell vectors; per-block partials to out[3*b + q]
 __global__ void k_dots(Sweep s, const double* a0, const double* b0, const double* a1, const double* b1,
                        const double* a2, const double* b2, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, a0, b0, a1, b1, a2, b2, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, a0, b0, out);
+    shift_all((size_t)blockIdx.y * s.bstride, a1, b1, a2, b2);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
@@ -1193,7 +1210,7 @@ __global__ void k_dots(Sweep s, const double* a0, const double* b0, const double
 
 // sums of the three velocity planes; per-block partials to out[3*b + c]
 __global__ void k_face_sums(Sweep s, const double* __restrict__ u, double* __restrict__ out) {
-    shift_all((size_t)blockIdx.y * s.bstride, u, out);
+    shift_nn((size_t)blockIdx.y * s.bstride, u, out);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[3] = {0.0, 0.0, 0.0};
@@ -1213,7 +1230,7 @@ __global__ void k_face_sums(Sweep s, const double* __restrict__ u, double* __res
 // p += alpha d, r -= alpha q
 __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restrict__ r, const double* __restrict__ d,
                                const double* __restrict__ q, MemberScalars am) {
-    shift_all((size_t)blockIdx.y * s.bstride, p, r, d, q);
+    shift_nn((size_t)blockIdx.y * s.bstride, p, r, d, q);
     if (!member_active(s.active)) return;
     const double alpha = am.v[blockIdx.y];
     const Column c = sweep_column(s);
@@ -1227,7 +1244,7 @@ __global__ void k_outer_update(Sweep s, double* __restrict__ p, double* __restri
 
 // u += a v on all three planes
 __global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __restrict__ v, MemberScalars am) {
-    shift_all((size_t)blockIdx.y * s.bstride, u, v);
+    shift_nn((size_t)blockIdx.y * s.bstride, u, v);
     if (!member_active(s.active)) return;
     const double a = am.v[blockIdx.y];
     const Column c = sweep_column(s);
@@ -1242,7 +1259,7 @@ __global__ void k_axpy_faces(Sweep s, double* __restrict__ u, const double* __re
 
 // dst = src (cells), for the members in s.active
 __global__ void k_copy_cells(Sweep s, double* __restrict__ dst, const double* __restrict__ src) {
-    shift_all((size_t)blockIdx.y * s.bstride, dst, src);
+    shift_nn((size_t)blockIdx.y * s.bstride, dst, src);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     if (!c.valid) return;
@@ -1254,7 +1271,7 @@ __global__ void k_copy_cells(Sweep s, double* __restrict__ dst, const double* __
 
 // d = z + beta d
 __global__ void k_dir_cells(Sweep s, double* __restrict__ d, const double* __restrict__ z, MemberScalars bm) {
-    shift_all((size_t)blockIdx.y * s.bstride, d, z);
+    shift_nn((size_t)blockIdx.y * s.bstride, d, z);
     if (!member_active(s.active)) return;
     const double beta = bm.v[blockIdx.y];
     const Column c = sweep_column(s);
@@ -1285,7 +1302,8 @@ __device__ __forceinline__ int label_at(const uint16_t* label, const uint32_t* b
 __global__ void k_comp_sum(const double* __restrict__ x, const uint16_t* __restrict__ label,
                            const uint32_t* __restrict__ bits, int N, int wpr, int64_t n3, int K, int64_t chunk,
                            double* __restrict__ part, size_t bstride, unsigned active) {
-    shift_all((size_t)blockIdx.y * bstride, x, label, bits, part);
+    shift_nn((size_t)blockIdx.y * bstride, x, bits, part);
+    shift_all((size_t)blockIdx.y * bstride, label);
     if (!member_active(active)) return;
     extern __shared__ double bins[];  // [kWaves][K]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1321,7 +1339,7 @@ __global__ void k_comp_sum(const double* __restrict__ x, const uint16_t* __restr
 
 __global__ void k_comp_mean(const double* __restrict__ part, int nblk, int K, const double* __restrict__ count,
                             double* __restrict__ mean, size_t bstride, unsigned active) {
-    shift_all((size_t)blockIdx.y * bstride, part, count, mean);
+    shift_nn((size_t)blockIdx.y * bstride, part, count, mean);
     if (!member_active(active)) return;
     const int L = blockIdx.x * kBlock + threadIdx.x;
     if (L >= K) return;
@@ -1333,7 +1351,8 @@ __global__ void k_comp_mean(const double* __restrict__ part, int nblk, int K, co
 __global__ void k_comp_sub(double* __restrict__ x, const uint16_t* __restrict__ label,
                            const uint32_t* __restrict__ bits, int N, int wpr, int64_t n3,
                            const double* __restrict__ mean, size_t bstride, unsigned active) {
-    shift_all((size_t)blockIdx.y * bstride, x, label, bits, mean);
+    shift_nn((size_t)blockIdx.y * bstride, x, bits, mean);
+    shift_all((size_t)blockIdx.y * bstride, label);
     if (!member_active(active)) return;
     for (int64_t X = (int64_t)blockIdx.x * kBlock + threadIdx.x; X < n3; X += (int64_t)gridDim.x * kBlock) {
         const int l = label_at(label, bits, N, wpr, X);
@@ -1347,7 +1366,7 @@ __global__ void k_comp_sub(double* __restrict__ x, const uint16_t* __restrict__ 
 // in block order (bit-identical mean in every block) and subtracts the mean at
 // the fluid cells: two sweeps instead of three latency-bound kernels.
 __global__ void k_sum1(Sweep s, const double* __restrict__ x, double* __restrict__ part) {
-    shift_all((size_t)blockIdx.y * s.bstride, x, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, x, part);
     if (!member_active(s.active)) return;
     const Column c = sweep_column(s);
     double acc[1] = {0.0};
@@ -1358,7 +1377,7 @@ __global__ void k_sum1(Sweep s, const double* __restrict__ x, double* __restrict
 
 __global__ void k_sub_mean1(Sweep s, double* __restrict__ x, const uint32_t* __restrict__ bits, int wpr,
                             const double* __restrict__ part, double inv_count) {
-    shift_all((size_t)blockIdx.y * s.bstride, x, bits, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, x, bits, part);
     if (!member_active(s.active)) return;
     const int slots[1] = {0};
     double tot[1];

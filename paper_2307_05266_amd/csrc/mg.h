@@ -78,7 +78,7 @@ __device__ __forceinline__ void fine_coeffs(const uint8_t* __restrict__ code, co
 template <class T>
 __global__ void k_mg_coarsen_fine(MgGrid fg, MgGrid cg, int kind, const uint8_t* __restrict__ code,
                                   T* __restrict__ D, T* __restrict__ Wx, T* __restrict__ Wy, T* __restrict__ Wz) {
-    shift_all((size_t)blockIdx.y * fg.bstride, code, D, Wx, Wy, Wz);
+    shift_nn((size_t)blockIdx.y * fg.bstride, code, D, Wx, Wy, Wz);
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= cg.nb * cg.n3) return;
     const int p = I / cg.n3, L = I - p * cg.n3;
@@ -105,7 +105,7 @@ template <class T>
 __global__ void k_mg_coarsen(MgGrid fg, MgGrid cg, const T* __restrict__ Df, const T* __restrict__ Wxf,
                              const T* __restrict__ Wyf, const T* __restrict__ Wzf, T* __restrict__ D,
                              T* __restrict__ Wx, T* __restrict__ Wy, T* __restrict__ Wz) {
-    shift_all((size_t)blockIdx.y * fg.bstride, Df, Wxf, Wyf, Wzf, D, Wx, Wy, Wz);
+    shift_nn((size_t)blockIdx.y * fg.bstride, Df, Wxf, Wyf, Wzf, D, Wx, Wy, Wz);
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= cg.nb * cg.n3) return;
     const int p = I / cg.n3, L = I - p * cg.n3;
@@ -291,7 +291,8 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
                                                       const T* __restrict__ invd, const T* __restrict__ b,
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       double* part, int slot, const CgState* st) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, invd, b, xc, out, part, st);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, b, out);
+    shift_all((size_t)blockIdx.y * s.bstride, invd, xc, part, st);
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
@@ -443,7 +444,8 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
                                                                 const T* __restrict__ d, const T* __restrict__ q,
                                                                 T* __restrict__ bc, T omega, CgState* st,
                                                                 double* part) {
-    shift_all((size_t)blockIdx.y * s.bstride, code, invd, x, r, rout, d, q, bc, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code, x, r, rout, d, q, bc, st, part);
+    shift_all((size_t)blockIdx.y * s.bstride, invd);
     constexpr int NB = MgfPt<T, KIND>::NB;
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[NB * kBlock / 2];
@@ -587,7 +589,8 @@ __device__ __forceinline__ T mgc_apply(const MgcPoint<T>& m, const T (&v)[7]) {
 template <class T>
 __global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict__ b, T* __restrict__ bc, T omega,
                                const CgState* st) {
-    shift_all((size_t)blockIdx.y * g.bstride, b, bc, st);
+    shift_nn((size_t)blockIdx.y * g.bstride, b, bc);
+    shift_all((size_t)blockIdx.y * g.bstride, st);
     shift_op(op, (size_t)blockIdx.y * g.bstride);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int I = t >> 3, ch = t & 7;
@@ -617,7 +620,8 @@ __global__ void k_mgc_restrict(MgGrid g, MgGrid cg, MgOp op, const T* __restrict
 template <class T>
 __global__ void k_mgc_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b, const T* __restrict__ xc, int cn,
                                  T scale, T omega, T* __restrict__ y, const CgState* st) {
-    shift_all((size_t)blockIdx.y * g.bstride, b, xc, y, st);
+    shift_nn((size_t)blockIdx.y * g.bstride, b, xc, y);
+    shift_all((size_t)blockIdx.y * g.bstride, st);
     shift_op(op, (size_t)blockIdx.y * g.bstride);
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= g.nb * g.n3) return;
@@ -769,7 +773,8 @@ template <class T>
 __global__ void __launch_bounds__(kGsThreads) k_mgc_gs_restrict(MgGrid g, MgGrid cg, MgOp op,
                                                                 const T* __restrict__ b, T* __restrict__ bc,
                                                                 const CgState* st) {
-    shift_all((size_t)blockIdx.y * g.bstride, b, bc, st);
+    shift_nn((size_t)blockIdx.y * g.bstride, b, bc);
+    shift_all((size_t)blockIdx.y * g.bstride, st);
     shift_op(op, (size_t)blockIdx.y * g.bstride);
     __shared__ T sx[kGsWin];
     const GsBrick k = gs_brick(g);
@@ -822,7 +827,8 @@ template <class T>
 __global__ void __launch_bounds__(kGsThreads) k_mgc_gs_postsmooth(MgGrid g, MgOp op, const T* __restrict__ b,
                                                                   const T* __restrict__ xc, int cn, T scale,
                                                                   T* __restrict__ y, const CgState* st) {
-    shift_all((size_t)blockIdx.y * g.bstride, b, xc, y, st);
+    shift_nn((size_t)blockIdx.y * g.bstride, b, xc, y);
+    shift_all((size_t)blockIdx.y * g.bstride, st);
     shift_op(op, (size_t)blockIdx.y * g.bstride);
     __shared__ T sx[kGsWin];
     const GsBrick k = gs_brick(g);
@@ -900,7 +906,8 @@ template <class T, int NB, bool POST>
 __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, const T* __restrict__ b,
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       const CgState* st) {
-    shift_all((size_t)blockIdx.y * s.bstride, b, xc, out, st);
+    shift_nn((size_t)blockIdx.y * s.bstride, b, out);
+    shift_all((size_t)blockIdx.y * s.bstride, xc, st);
     shift_op(op, (size_t)blockIdx.y * s.bstride);
     __shared__ T tile[2][NB][kTileMax];
     __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
@@ -988,7 +995,8 @@ constexpr int kMgCoarsestPer = kMgCoarsestMax / kMgCoarsestThreads;
 template <class T>
 __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __restrict__ xout, T omega, int sweeps,
                               const CgState* st) {
-    shift_all((size_t)blockIdx.y * g.bstride, b, xout, st);
+    shift_nn((size_t)blockIdx.y * g.bstride, b, xout);
+    shift_all((size_t)blockIdx.y * g.bstride, st);
     shift_op(op, (size_t)blockIdx.y * g.bstride);
     __shared__ T xs[2][kMgCoarsestMax];
     const int n = g.nb * g.n3;
@@ -1051,7 +1059,7 @@ __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __r
 
 // out = (float) in, flat
 __global__ void k_narrow_flat(int n, const double* __restrict__ in, float* __restrict__ out, size_t bstride) {
-    shift_all((size_t)blockIdx.y * bstride, in, out);
+    shift_nn((size_t)blockIdx.y * bstride, in, out);
     for (int X = blockIdx.x * blockDim.x + threadIdx.x; X < n; X += gridDim.x * blockDim.x) out[X] = (float)in[X];
 }
 
