@@ -112,6 +112,50 @@ def precond_study(P, cases=None):
         print(json.dumps(row), flush=True)
 
 
+def slit_study(P, torch, N=128, widths=(4, 6, 8, 12, 16, 24, 32), seeds=(0, 1, 2)):
+    """The 128^3 slit stacks (walls 2 voxels thick, normal to y, channel width W):
+    (i) force along the channels (g = 0: no outer step, plane Poiseuille flux),
+    (ii) oblique force (1, 0.5, 0) (the flux of (i), pressure steps of f_y),
+    (iii) random consistent right-hand sides g = B xi (xi seeded, standard
+    normal on the faces) for the outer counts against the surface-to-volume
+    ratio; FP64, tol 1e-8, both preconditioners.  One JSON line per width."""
+    import numpy as np
+
+    from synth import random_face_field, slits
+    from synth.geometry import channel_widths
+    for W in widths:
+        m = slits(N, W, 2, 1)
+        ws = channel_widths(N, W)
+        kx = sum(w * (w * w + 2) / 12.0 for w in ws) / N
+        row = {"study": "slits", "N": N, "W": W, "channels": len(ws), "kvox_closed_form": kx}
+        with P.Stokes(m, (1.0, 0.0, 0.0)) as s:
+            info = s.info()
+            row["stv_ratio"] = info["nsurf"] / info["nfluid_in"]
+            for pc in ("simple", "uzawa"):
+                rep = s.solve(pc, 1e-8)
+                row[f"i_{pc}"] = {"outer": rep["outer_iters"], "kvox_rel_err": abs(rep["k_vox"] - kx) / kx,
+                                  "zero_rhs": bool(rep["flags"] & P.STOKES_FLAG_ZERO_RHS)}
+            for q in seeds:
+                xi = torch.tensor(random_face_field(N, q).reshape(-1), dtype=torch.float64, device="cuda")
+                g = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+                s.apply_device(P.STOKES_OP_B, xi, g)
+                gh = g.cpu().numpy()
+                for pc in ("simple", "uzawa"):
+                    t0 = time.perf_counter()
+                    rep = s.solve_rhs(gh, pc, 1e-8)
+                    row.setdefault(f"iii_{pc}_outer", []).append(rep["outer_iters"])
+                    row.setdefault(f"iii_{pc}_seconds", []).append(time.perf_counter() - t0)
+        with P.Stokes(m, (1.0, 0.5, 0.0)) as s:
+            for pc in ("simple", "uzawa"):
+                rep = s.solve(pc, 1e-8)
+                row[f"ii_{pc}"] = {"outer": rep["outer_iters"],
+                                   "kvox_x_rel_err": abs(rep["mean_u"][0] - kx) / kx,
+                                   "mean_u_y": rep["mean_u"][1]}
+        log(f"[slits] W={W} stv={row['stv_ratio']:.3f} (iii) outer simple {row['iii_simple_outer']} "
+            f"uzawa {row['iii_uzawa_outer']}")
+        print(json.dumps(row), flush=True)
+
+
 def batch_study(P, torch, members=(1, 4, 8, 16, 32), sides=(32, 48, 64)):
     """Mixed-precision SIMPLE solves of small boxes (spheres r=3, porosity 0.45):
     one batched context of B members against B contexts of one member solved
@@ -426,7 +470,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS)
     ap.add_argument("--serve-members", type=int, default=32,
                     help="requests per batched context in the server (1 = no batching)")
-    ap.add_argument("--study", choices=["precond", "precond256", "batch"],
+    ap.add_argument("--study", choices=["precond", "precond256", "batch", "slits"],
                     help="instead of the benchmark: SIMPLE against Uzawa over 128^3 geometries (precond), or "
                          "batched contexts against one context per request for small boxes (batch)")
     args = ap.parse_args()
@@ -458,6 +502,9 @@ def main():
         return
     if args.study == "batch":
         batch_study(P, torch)
+        return
+    if args.study == "slits":
+        slit_study(P, torch)
         return
     if args.serve_only:
         sv = serve(P, reqs, slots=args.serve_slots, max_members=args.serve_members)

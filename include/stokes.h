@@ -287,6 +287,20 @@ stokes_status stokes_set_option(stokes_ctx *ctx, const char *key, double value);
  */
 stokes_status stokes_solve(stokes_ctx *ctx, stokes_precond precond, double tol, stokes_report *report);
 
+/*
+ * stokes_solve_rhs -- CG on S p = g for a given right-hand side (the
+ * Schur-complement system of Sec. 1, eq. schur_system, with g from the caller
+ * instead of g = B A^{-1} f): g is a host array of N^3 doubles, read on the
+ * fluid cells during the call, and must lie in the range of B (e.g. g = B xi,
+ * which makes it sum to zero over every component).  Starts from p = 0 and
+ * u = 0, so the returned velocity is -A^{-1} B^T p and the report's
+ * permeability fields refer to it.  Only an exactly zero g skips the loop.
+ * FP64 plain contexts only: STOKES_E_STATE for a batched context or with
+ * "precision" 1; otherwise as stokes_solve.
+ */
+stokes_status stokes_solve_rhs(stokes_ctx *ctx, stokes_precond precond, double tol, const double *g,
+                               stokes_report *report);
+
 /* Permeability of the last solve along the force, non-dimensional (Sec. 2.3):
  * k_hat = <u . f> / |f|^2 / N^2.  STOKES_E_STATE before a solve. */
 stokes_status stokes_permeability(stokes_ctx *ctx, double *k_hat);

@@ -64,6 +64,8 @@ def _load():
     lib.oracle_solve.argtypes = [vp, ip, dp, ctypes.c_void_p, ctypes.c_void_p, dp,
                                  ctypes.c_void_p, ip]
     lib.oracle_solve.restype = ip
+    lib.oracle_solve_g.argtypes = [vp, ip, dp, dp, ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_void_p, ip]
+    lib.oracle_solve_g.restype = ip
     lib.oracle_inner_solve.argtypes = [vp, ip, dp, dp, ctypes.c_double, ip]
     lib.oracle_inner_solve.restype = ip
     lib.oracle_threads.restype = ip
@@ -191,7 +193,10 @@ class Oracle:
 
     # ---- the solve ------------------------------------------------------------
     def solve(self, precond=SIMPLE, tol=1e-8, eps_A=1e-12, eps_S=1e-12, max_outer=2000,
-              max_inner=200000, stop_prec=False, true_u=False, hist_cap=4000, zero_rhs_factor=1000.0):
+              max_inner=200000, stop_prec=False, true_u=False, hist_cap=4000, zero_rhs_factor=1000.0,
+              g=None):
+        """g: optional right-hand side of S p = g (N^3 cell field) in place of
+        g = B A^-1 f; the loop then starts from u0 = 0."""
         N = self.N
         params = np.array([tol, eps_A, eps_S, max_outer, max_inner, int(stop_prec),
                            int(true_u), zero_rhs_factor], dtype=np.float64)
@@ -199,8 +204,14 @@ class Oracle:
         u = np.zeros(3 * N ** 3)
         stats = np.zeros(24)
         hist = np.zeros((hist_cap, 8))
-        st = _load().oracle_solve(self._h, int(precond), _dptr(params), p.ctypes.data,
-                                  u.ctypes.data, _dptr(stats), hist.ctypes.data, hist_cap)
+        if g is None:
+            st = _load().oracle_solve(self._h, int(precond), _dptr(params), p.ctypes.data,
+                                      u.ctypes.data, _dptr(stats), hist.ctypes.data, hist_cap)
+        else:
+            gd = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+            assert gd.size == N ** 3
+            st = _load().oracle_solve_g(self._h, int(precond), _dptr(params), _dptr(gd), p.ctypes.data,
+                                        u.ctypes.data, _dptr(stats), hist.ctypes.data, hist_cap)
         k = int(stats[2])
         h = hist[:min(k, hist_cap)]
         res = {

@@ -697,8 +697,21 @@ static double khat_of(const osys_t *s, const double *u, double mean_out[3])
     return fu / f2;                       /* permeability in voxel units */
 }
 
+/* As oracle_solve, with a given right-hand side: g_dense (N^3 doubles, read on
+ * the fluid cells) replaces g = B A^{-1} f, the loop starts from p0 = 0 and
+ * u0 = 0 (the recursive velocity is then -A^{-1} B^T p), and only an exactly
+ * zero g skips the loop.  g_dense == NULL is oracle_solve itself. */
+int oracle_solve_g(const osys_t *s, int precond, const double *params, const double *g_dense,
+                   double *p_dense, double *u_dense, double *stats, double *hist, int hist_cap);
+
 int oracle_solve(const osys_t *s, int precond, const double *params,
                  double *p_dense, double *u_dense, double *stats, double *hist, int hist_cap)
+{
+    return oracle_solve_g(s, precond, params, NULL, p_dense, u_dense, stats, hist, hist_cap);
+}
+
+int oracle_solve_g(const osys_t *s, int precond, const double *params, const double *g_dense,
+                   double *p_dense, double *u_dense, double *stats, double *hist, int hist_cap)
 {
     const long nf = s->nf, nc = s->nc;
     const double tol = params[0], epsA = params[1], epsS = params[2];
@@ -727,9 +740,14 @@ int oracle_solve(const osys_t *s, int precond, const double *params,
 
     for (long i = 0; i < nf; ++i) f[i] = s->force[s->face_pos[i] / s->n3];
 
-    /* p0 = 0: u0 = A^{-1} f, r0 = g - S p0 = B u0 */
-    innerA += pcg(&opA, nf, s->diagA, f, u, epsA, max_inner, &inner_st);
-    spmv(&s->B, u, r);
+    if (g_dense) {
+        /* p0 = 0, u0 = 0: r0 = g */
+        gather_cells(s, g_dense, r);
+    } else {
+        /* p0 = 0: u0 = A^{-1} f, r0 = g - S p0 = B u0 */
+        innerA += pcg(&opA, nf, s->diagA, f, u, epsA, max_inner, &inner_st);
+        spmv(&s->B, u, r);
+    }
     project(s, r);
 
 #define PRECOND(rr, zz)                                                         \
@@ -747,7 +765,7 @@ int oracle_solve(const osys_t *s, int precond, const double *params,
     double r0 = nrm2(nc, r), z0 = nrm2(nc, z);
     double rel = 0.0, relz = 0.0;
     double fu0 = dot(nf, f, u);
-    double g_floor = fu0 > 0.0 ? zero_rhs_factor * epsA * sqrt(fu0) : 0.0;
+    double g_floor = (fu0 > 0.0 && !g_dense) ? zero_rhs_factor * epsA * sqrt(fu0) : 0.0;
     int k = 0;
     if (r0 > g_floor) {
         for (k = 0; k < max_outer;) {

@@ -1439,7 +1439,7 @@ static void report_progress(stokes_ctx* c, int k, double rel, double k_hat) {
     std::fflush(stderr);
 }
 
-static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double tol) {
+static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double tol, const double* g_host = nullptr) {
     stokes_report& R = c->rep;
     const Sweep& s = c->sw;
     const int64_t n3 = c->n3;
@@ -1473,16 +1473,25 @@ static stokes_status solve_impl(stokes_ctx* c, stokes_precond precond, double to
         else if (st == 1) R.flags |= STOKES_FLAG_INNER_MAXIT;
     };
 
-    // u0 = A^{-1} f
-    ST_TRY(solve_A64(c, nullptr, c->eps_A, &itA, &stA));
-    totA += itA;
-    note_inner(stA);
-    std::swap(c->u, c->fx);
     double g_floor = 0.0;
-    ST_TRY(rhs_floor(c, c->eps_A, &g_floor));
-    // r0 = g - S 0 = B u0
-    hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
-    HIP_TRY(hipGetLastError());
+    if (g_host) {
+        // a given right-hand side: p0 = 0, u0 = 0, r0 = g on the fluid cells
+        // (only an exactly zero g skips the loop)
+        HIP_TRY(hipMemsetAsync(c->u, 0, (size_t)(3 * n3) * sizeof(double), c->stream));
+        HIP_TRY(hipMemcpyAsync(c->r, g_host, (size_t)n3 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_mask_cells, grid_of(s), dim3(kBlock), 0, c->stream, s, c->bits, c->wpr, c->r);
+        HIP_TRY(hipGetLastError());
+    } else {
+        // u0 = A^{-1} f
+        ST_TRY(solve_A64(c, nullptr, c->eps_A, &itA, &stA));
+        totA += itA;
+        note_inner(stA);
+        std::swap(c->u, c->fx);
+        ST_TRY(rhs_floor(c, c->eps_A, &g_floor));
+        // r0 = g - S 0 = B u0
+        hipLaunchKernelGGL(k_apply_B, grid_of(s), dim3(kBlock), 0, c->stream, s, c->u, c->r);
+        HIP_TRY(hipGetLastError());
+    }
     ST_TRY(project(c, c->r));
     double* z = c->r;
     if (precond == STOKES_SIMPLE) {
@@ -1977,6 +1986,25 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->rep.seconds = secs;
     for (auto& r : c->mrep) r.seconds = secs;
+    if (report) *report = c->rep;
+    return st;
+}
+
+stokes_status stokes_solve_rhs(stokes_ctx* c, stokes_precond precond, double tol, const double* g,
+                               stokes_report* report) {
+    if (!c || !g) return STOKES_E_ARG;
+    if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
+    if (c->batch_api || c->precision != 0) return STOKES_E_STATE;
+    const auto t0 = std::chrono::steady_clock::now();
+    c->t_solve0 = t0;
+    stokes_status st;
+    try {
+        st = solve_impl(c, precond, tol, g);
+    } catch (const std::bad_alloc&) {
+        st = STOKES_E_NOMEM;
+    }
+    c->rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (report) *report = c->rep;
     return st;
 }

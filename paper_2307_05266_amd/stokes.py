@@ -33,7 +33,7 @@ EXPORTED = [
     "stokes_apply", "stokes_apply_device", "stokes_info", "stokes_kernel_timing",
     "stokes_destroy", "stokes_status_str", "stokes_preprocess", "stokes_setup_on_stream",
     "stokes_estimate_bytes", "stokes_apply_device_noalloc", "stokes_setup_with_allocator",
-    "stokes_setup_batch", "stokes_batch_result",
+    "stokes_setup_batch", "stokes_batch_result", "stokes_solve_rhs",
 ]
 EXPORTED_SERVER = [
     "stokes_server_create", "stokes_server_submit", "stokes_server_wait", "stokes_server_stats",
@@ -160,6 +160,7 @@ def load():
                                          ctypes.POINTER(StokesAllocator)], ip),
         "stokes_setup_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ip, ip, dp, ctypes.c_uint, vp], ip),
         "stokes_batch_result": ([vp, ip, ctypes.POINTER(StokesReport), vp, vp], ip),
+        "stokes_solve_rhs": ([vp, ip, ctypes.c_double, vp, ctypes.POINTER(StokesReport)], ip),
         "stokes_estimate_bytes": ([ip, ctypes.c_uint, ip, i64p], ip),
         "stokes_server_create": ([ctypes.POINTER(vp), ip, ctypes.c_int64], ip),
         "stokes_server_submit": ([vp, vp, ip, dp, ip, ctypes.c_double, ip, i64p], ip),
@@ -385,6 +386,18 @@ class Stokes:
             precond = {"uzawa": STOKES_UZAWA, "simple": STOKES_SIMPLE}[precond.lower()]
         st, rep = stokes_solve(self._ctx, precond, tol)
         return rep
+
+    def solve_rhs(self, g, precond=STOKES_SIMPLE, tol=1e-8):
+        """CG on S p = g for a given g (N^3 cells, in the range of B); FP64."""
+        if isinstance(precond, str):
+            precond = {"uzawa": STOKES_UZAWA, "simple": STOKES_SIMPLE}[precond.lower()]
+        gd = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+        if gd.size != self.N ** 3:
+            raise ValueError("g must hold N^3 values")
+        rep = StokesReport()
+        st = load().stokes_solve_rhs(self._ctx, int(precond), float(tol), gd.ctypes.data, ctypes.byref(rep))
+        _check(st, "stokes_solve_rhs", ok=(STOKES_OK, STOKES_NOT_CONVERGED))
+        return rep.to_dict()
 
     def permeability(self):
         return stokes_permeability(self._ctx)

@@ -550,3 +550,49 @@ def test_sampled_residuals_match_assembled_operators(oracle_mod):
         r = o.solve(oracle.SIMPLE, tol=1e-12)
         rf, rc = oracle.sample_residuals(light, r["u"], r["p"], fpos, cpos)
         assert np.nanmax(np.abs(rf)) < 1e-8 and np.nanmax(np.abs(rc)) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# Given right-hand sides g = B xi (consistent: in the range of B), the outer
+# loop started from p = 0, u = 0: the random-consistent-RHS runs of the slit
+# stacks (outer counts against the surface-to-volume ratio)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,seed,phi", [(6, 1, 0.7), (7, 2, 0.6), (8, 3, 0.65)])
+def test_given_rhs_solves_schur_system(oracle_mod, N, seed, phi):
+    """p from the outer PCG with g = B xi equals a dense least-squares solve of
+    S p = g with S = B A^-1 B^T formed from the assembled matrices, per-component
+    means removed; the residual B A^-1 B^T p - g vanishes."""
+    rng = np.random.default_rng(seed)
+    m = (rng.random((N, N, N)) < phi).astype(np.uint8)
+    o = oracle.Oracle(m, (1.0, 0.0, 0.0), strip=False)
+    xi = rng.standard_normal((3, N, N, N))
+    g = o.apply(oracle.OP_B, xi)
+    A = o.csr("A").toarray()
+    B = o.csr("B").toarray()
+    _, cpos = o.unknowns()
+    S = B @ np.linalg.solve(A, B.T)
+    gv = g.reshape(-1)[cpos]
+    pv, *_ = np.linalg.lstsq(S, gv, rcond=None)
+    comp = o.masks()[1].reshape(-1)[cpos]
+    for c in np.unique(comp):
+        pv[comp == c] -= pv[comp == c].mean()
+    for pc in (oracle.UZAWA, oracle.SIMPLE):
+        r = o.solve(pc, tol=1e-12, eps_A=1e-14, eps_S=1e-14, g=g)
+        assert r["status"] == 0 and r["outer_iters"] > 0
+        p = r["p"].reshape(-1)[cpos]
+        assert np.abs(p - pv).max() <= 1e-8 * np.abs(pv).max()
+        assert np.abs(S @ p - gv).max() <= 1e-9 * np.abs(gv).max()
+
+
+def test_given_rhs_equal_to_force_rhs(oracle_mod):
+    """With g = B A^-1 f the given-RHS loop reaches the pressure of the ordinary solve."""
+    m = spheres(12, 2.0, 0.6, 4)
+    o = oracle.Oracle(m, (1.0, 0.0, 0.0))
+    a = o.solve(oracle.SIMPLE, **TIGHT)
+    f = np.zeros((3, 12, 12, 12))
+    f[0] = o.apply(oracle.OP_DIAG_A, None)[0] > 0
+    u0, _ = o.inner_solve(0, f, eps=1e-14)
+    g = o.apply(oracle.OP_B, u0)
+    b = o.solve(oracle.SIMPLE, g=g, **TIGHT)
+    assert np.abs(a["p"] - b["p"]).max() <= 1e-8 * np.abs(a["p"]).max()
+    assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
