@@ -279,6 +279,19 @@ def host_cpu_model():
     return "unknown CPU"
 
 
+# The FP64 SIMPLE solve runs these sweeps in their software-pipelined forms
+# (the library's default, option mg_pipe); the timing kinds keep the plain names.
+PIPELINED_SYMBOLS = {"k_mgf_update_restrict<S>": "k_mgf_update_restrict_S_pipe<double>",
+                     "k_mgf_tiled<S,smooth>": "k_mgf_smooth_S_pipe<double>",
+                     "k_cgS_dirstencil_tiled": "k_cgS_dirstencil_pipe<double>"}
+
+
+def kernel_symbol(kind_name, precision):
+    if precision == "fp64" and kind_name in PIPELINED_SYMBOLS:
+        return PIPELINED_SYMBOLS[kind_name]
+    return kind_name
+
+
 def cpu_baseline(workload, mask, gpu_rep, iters=30):
     """The oracle's cost per solve on the same geometry: its cost per inner A and
     per inner SIMPLE iteration, timed here on the host cores over a bounded run of
@@ -616,6 +629,8 @@ def main():
                                      sweeps_S * info["nfluid"]) * args.steps / total,
         "roofline": {
             "kernel": dom,
+            # the code object that ran for that sweep (as rocprofv3 names it)
+            "symbol": kernel_symbol(dom, args.precision),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -242,6 +242,12 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 the direction is double-buffered); 0: a separate pointwise
  *                 direction kernel, then the stencil.  Same results bitwise.
  *                 Defaults: 0 for A, 1 for the SIMPLE matrix.
+ *   "mg_pipe"     1 (default): the FP64 multigrid-preconditioned solve with the
+ *                 SIMPLE matrix runs its three level-0 sweeps (direction and
+ *                 stencil, update and restriction, post-smoothing) with their
+ *                 loads issued one z-plane ahead of their use; 0: the plain
+ *                 forms.  Same arithmetic point by point, results bitwise the
+ *                 same.  FP32 inner solves always use the plain forms.
  *   "progress"    n > 0: one line on stderr every n outer iterations
  *                 (iteration, relative residual, permeability, elapsed
  *                 seconds); 0 = silent (default)

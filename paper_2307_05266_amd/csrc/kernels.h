@@ -997,6 +997,92 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_tiled(Sweep s, const 
     write_partials<1>(acc, part, kDQ, t.lb);
 }
 
+// k_cgS_dirstencil_tiled with its loads software-pipelined over the z-march:
+// at plane k a thread issues the loads of its own column at k + 2 (code, z,
+// din) and of its ring point at k + 1, and forms the direction from the values
+// loaded one plane earlier, so the loads have a whole plane to arrive; the
+// codes of the +x and +y neighbours come from an LDS tile.  Same arithmetic as
+// the unpipelined kernel, point by point.
+template <class T>
+struct CgsRaw {
+    int cd;
+    T z, di;
+};
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const uint8_t* __restrict__ code,
+                                                                const T* __restrict__ z, const T* __restrict__ din,
+                                                                T* __restrict__ dout, T* __restrict__ q, CgState* st,
+                                                                double* part) {
+    shift_nn((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
+    if (st->done) return;
+    double beta_d;
+    int j;
+    if (cg_dir_scalars(st, part, s.nblk, &beta_d, &j)) return;
+    const T beta = (T)beta_d;
+    const bool first = j == 0;
+    __shared__ T tl[2][kTileMax];
+    __shared__ int ctl[2][kTileMax];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    const Tile t = tile_of(s);
+    const int N = t.N, N2 = N * N, W = t.W, own = t.own, hslot = t.hslot;
+    const bool ring = t.ring;
+    const int col = t.wi + N * t.wj;
+    const int hcol = t.hi + N * t.hj;
+    // din is read also when the first iteration ignores it (an allocated
+    // vector), so no branch on the iteration sits between the loads
+    auto load = [&](CgsRaw<T>& w, int X) {
+        w.cd = code[X];
+        w.z = z[X];
+        w.di = din[X];
+    };
+    auto dn = [&](const CgsRaw<T>& w) -> T { return first ? w.z : w.z + beta * w.di; };
+    CgsRaw<T> ra, rb, ha, hb;
+    load(ra, col + tile_zw(t.k0 - 1, N) * N2);
+    load(rb, col + t.k0 * N2);
+    T dprev = dn(ra), dcur = dn(rb);
+    int ccur = rb.cd;
+    load(ra, col + tile_zw(t.k0 + 1, N) * N2);
+    if (ring) load(ha, hcol + t.k0 * N2);
+    double acc[1] = {0.0};
+    int buf = 0;
+    auto plane = [&](int k, const CgsRaw<T>& rfin, CgsRaw<T>& rload, const CgsRaw<T>& hfin, CgsRaw<T>& hload) {
+        load(rload, col + tile_zw(k + 2, N) * N2);
+        if (ring) load(hload, hcol + tile_zw(k + 1, N) * N2);
+        const T dnext = dn(rfin);
+        const int cnext = rfin.cd;
+        if (ring) {
+            tl[buf][hslot] = dn(hfin);
+            ctl[buf][hslot] = hfin.cd;
+        }
+        tl[buf][own] = dcur;
+        ctl[buf][own] = ccur;
+        __syncthreads();
+        const T* w = tl[buf];
+        const int cxp = ctl[buf][own + 1], cyp = ctl[buf][own + W];
+        const T qv = ((ft.inv[0][ccur] * (dcur - w[own - 1]) + ft.inv[0][cxp] * (dcur - w[own + 1])) +
+                      (ft.inv[1][ccur] * (dcur - w[own - W]) + ft.inv[1][cyp] * (dcur - w[own + W]))) +
+                     (ft.inv[2][ccur] * (dcur - dprev) + ft.inv[2][cnext] * (dcur - dnext));
+        if (t.valid) {
+            dout[col + k * N2] = dcur;
+            q[col + k * N2] = qv;
+            acc[0] += (double)dcur * (double)qv;
+        }
+        dprev = dcur;
+        dcur = dnext;
+        ccur = cnext;
+        buf ^= 1;
+    };
+    int k = t.k0;
+    for (; k + 1 < t.k1; k += 2) {
+        plane(k, ra, rb, ha, hb);
+        plane(k + 1, rb, ra, hb, ha);
+    }
+    if (k < t.k1) plane(k, ra, rb, ha, hb);
+    write_partials<1>(acc, part, kDQ, t.lb);
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cgA_dirstencil_tiled(Sweep s, const uint8_t* __restrict__ code,
                                                                  const T* __restrict__ z, const T* __restrict__ din,

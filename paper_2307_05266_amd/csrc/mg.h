@@ -377,6 +377,120 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
     }
 }
 
+// The SIMPLE matrix's level-0 post-smoothing (k_mgf_tiled<T, kMgFineShat,
+// true>) with its loads software-pipelined over the z-march: at plane k a
+// thread issues the raw loads of its own column at k + 2 and of its ring point
+// at k + 1, and finishes the values loaded one plane earlier, so every load has
+// a whole plane (barrier and stencil) to arrive instead of being waited for in
+// the plane that issued it.  The codes of the +x and +y neighbours come from an
+// LDS tile filled beside the values.  Same arithmetic as the unpipelined
+// kernel, point by point.
+template <class T>
+struct MgfRawS {
+    int cd;
+    T inv, b, e;
+};
+
+template <class T>
+__device__ __forceinline__ void mgfs_load(MgfRawS<T>& q, int N, int cn, int i, int j, int k,
+                                          const uint8_t* __restrict__ code, const T* __restrict__ invd,
+                                          const T* __restrict__ b, const T* __restrict__ xc) {
+    const int X = i + N * (j + N * k);
+    q.cd = code[X];
+    q.inv = invd[X];
+    q.b = b[X];
+    q.e = xc[(i >> 1) + cn * ((j >> 1) + cn * (k >> 1))];
+}
+
+template <class T>
+__device__ __forceinline__ T mgfs_x(const MgfRawS<T>& q, T scale, T omega) {
+    T x = omega * q.inv * q.b;
+    if (q.inv > T(0)) x += scale * q.e;
+    return x;
+}
+
+template <class T>
+struct MgfPtS {
+    int cd;
+    T inv, b, x;
+};
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, const uint8_t* __restrict__ code,
+                                                              const T* __restrict__ invd, const T* __restrict__ b,
+                                                              const T* __restrict__ xc, T scale, T omega,
+                                                              T* __restrict__ out, double* part, int slot,
+                                                              const CgState* st) {
+    shift_nn((size_t)blockIdx.y * s.bstride, code, invd, b, xc, out, part);
+    shift_all((size_t)blockIdx.y * s.bstride, st);
+    __shared__ T tile[2][kTileMax];
+    __shared__ int ctile[2][kTileMax];
+    __shared__ FaceTab<T> ft;
+    face_tab_fill<T>(ft);
+    __syncthreads();
+    const Tile tt = tile_of(s);
+    const int N = tt.N, W = tt.W, lb = tt.lb;
+    const int wi = tt.wi, wj = tt.wj, k0 = tt.k0, k1 = tt.k1;
+    const int hi = tt.hi, hj = tt.hj, hslot = tt.hslot, own = tt.own;
+    auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
+    auto finish = [scale, omega](const MgfRawS<T>& q) {
+        MgfPtS<T> p;
+        p.cd = q.cd;
+        p.inv = q.inv;
+        p.b = q.b;
+        p.x = mgfs_x<T>(q, scale, omega);
+        return p;
+    };
+
+    // two sets of raw loads alternate between the planes of an unrolled pair,
+    // so no register that a load is still filling is copied at the loop's end
+    MgfRawS<T> ra, rb, ha, hb;
+    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 - 1), code, invd, b, xc);
+    mgfs_load<T>(rb, N, cn, wi, wj, k0, code, invd, b, xc);
+    const T x_first = mgfs_x<T>(ra, scale, omega);
+    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 + 1), code, invd, b, xc);
+    if (tt.ring) mgfs_load<T>(ha, N, cn, hi, hj, k0, code, invd, b, xc);
+    // a finished solve is checked after the first loads (in bounds either way)
+    if (st && st->done) return;
+    T xprev = x_first;
+    MgfPtS<T> cur = finish(rb);
+    double acc = 0.0;
+    int buf = 0;
+    // plane k: issue the loads of k + 2 (own) and k + 1 (ring), finish k + 1
+    // (own) and k (ring) from the loads issued one plane earlier
+    auto plane = [&](int k, const MgfRawS<T>& rfin, MgfRawS<T>& rload, const MgfRawS<T>& hfin, MgfRawS<T>& hload) {
+        mgfs_load<T>(rload, N, cn, wi, wj, zw(k + 2), code, invd, b, xc);
+        if (tt.ring) mgfs_load<T>(hload, N, cn, hi, hj, zw(k + 1), code, invd, b, xc);
+        const MgfPtS<T> nxt = finish(rfin);
+        if (tt.ring) {
+            tile[buf][hslot] = mgfs_x<T>(hfin, scale, omega);
+            ctile[buf][hslot] = hfin.cd;
+        }
+        tile[buf][own] = cur.x;
+        ctile[buf][own] = cur.cd;
+        __syncthreads();
+        const T* tl = tile[buf];
+        const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
+        const T ax = mgf_apply<T, kMgFineShat>(v, cur.cd, ctile[buf][own + 1], ctile[buf][own + W], nxt.cd, 0, ft);
+        const T yv = cur.inv > T(0) ? v[0] + omega * cur.inv * (cur.b - ax) : T(0);
+        if (tt.valid) {
+            out[wi + N * (wj + N * k)] = yv;
+            acc += (double)cur.b * (double)yv;
+        }
+        xprev = cur.x;
+        cur = nxt;
+        buf ^= 1;
+    };
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+        plane(k, ra, rb, ha, hb);
+        plane(k + 1, rb, ra, hb, ha);
+    }
+    if (k < k1) plane(k, ra, rb, ha, hb);
+    double v1[1] = {acc};
+    write_partials<1>(v1, part, slot, lb);
+}
+
 // The inner CG update fused with the level-0 restriction that follows it:
 // alpha from the stencil's partials, x += alpha d, rout = rin - alpha q, and
 // bc = P^T (rout - A x0), x0 = omega D^-1 rout, in one LDS-tiled sweep (the
@@ -534,6 +648,123 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
         cur = nxt;
         buf ^= 1;
     }
+    write_partials<2>(acc, part, kRZ, lb);
+}
+
+// The SIMPLE matrix's fused CG update and level-0 restriction
+// (k_mgf_update_restrict<T, kMgFineShat>) with its stencil loads
+// software-pipelined as in k_mgf_smooth_S_pipe: at plane k a thread issues the
+// loads of its own column at k + 2 (code, 1/D, r, q) and of its ring point at
+// k + 1, and finishes the values loaded one plane earlier.  x and d are read
+// where the update uses them
+// (measured at 256^3: x and d two planes ahead made this sweep slower).  Same arithmetic as the unpipelined
+// kernel, point by point.
+template <class T>
+struct MgfRawU {
+    int cd;
+    T inv, r, q;
+};
+
+template <class T>
+__device__ __forceinline__ void mgfu_load(MgfRawU<T>& w, int X, const uint8_t* __restrict__ code,
+                                          const T* __restrict__ invd, const T* __restrict__ r,
+                                          const T* __restrict__ q) {
+    w.cd = code[X];
+    w.inv = invd[X];
+    w.r = r[X];
+    w.q = q[X];
+}
+
+template <class T>
+__device__ __forceinline__ MgfPtS<T> mgfu_finish(const MgfRawU<T>& w, T alpha, T omega) {
+    MgfPtS<T> p;
+    p.cd = w.cd;
+    p.inv = w.inv;
+    p.b = w.r - alpha * w.q;
+    p.x = omega * p.inv * p.b;
+    return p;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, const uint8_t* __restrict__ code,
+                                                                       const T* __restrict__ invd, T* __restrict__ x,
+                                                                       const T* __restrict__ r, T* __restrict__ rout,
+                                                                       const T* __restrict__ d,
+                                                                       const T* __restrict__ q, T* __restrict__ bc,
+                                                                       T omega, CgState* st, double* part) {
+    shift_nn((size_t)blockIdx.y * s.bstride, code, invd, x, r, rout, d, q, bc, st, part);
+    __shared__ T tile[2][kTileMax];
+    __shared__ int ctile[2][kTileMax];
+    __shared__ T pair_lds[kBlock / 2];
+    __shared__ FaceTab<T> ft;
+    const Tile tt = tile_of(s);
+    const int N = tt.N, W = tt.W, lb = tt.lb;
+    const int gi = tt.gi, gj = tt.gj, wi = tt.wi, wj = tt.wj, k0 = tt.k0, k1 = tt.k1;
+    const bool valid = tt.valid, ring = tt.ring;
+    const int hslot = tt.hslot, own = tt.own;
+    const int N2 = N * N;
+    const int col = wi + N * wj, hcol = tt.hi + N * tt.hj;
+    auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
+    // the first planes' loads go out before alpha is reduced (in bounds
+    // whether or not the solve has finished)
+    MgfRawU<T> ra, rb, ha, hb;
+    mgfu_load<T>(ra, col + zw(k0 - 1) * N2, code, invd, r, q);
+    mgfu_load<T>(rb, col + k0 * N2, code, invd, r, q);
+    if (st->done) return;
+    double alpha_d;
+    if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
+    const T alpha = (T)alpha_d;
+    face_tab_fill<T>(ft);
+    __syncthreads();
+    T xprev = mgfu_finish<T>(ra, alpha, omega).x;
+    MgfPtS<T> cur = mgfu_finish<T>(rb, alpha, omega);
+    mgfu_load<T>(ra, col + zw(k0 + 1) * N2, code, invd, r, q);
+    if (ring) mgfu_load<T>(ha, hcol + k0 * N2, code, invd, r, q);
+    double acc[2] = {0.0, 0.0};
+    T rsum = T(0);
+    int buf = 0;
+    // plane k: issue the loads of k + 2 (own) and k + 1 (ring), finish k + 1
+    // (own) and k (ring) from the loads issued one plane earlier
+    auto plane = [&](int k, const MgfRawU<T>& rfin, MgfRawU<T>& rload, const MgfRawU<T>& hfin, MgfRawU<T>& hload) {
+        mgfu_load<T>(rload, col + zw(k + 2) * N2, code, invd, r, q);
+        if (ring) mgfu_load<T>(hload, hcol + zw(k + 1) * N2, code, invd, r, q);
+        const MgfPtS<T> nxt = mgfu_finish<T>(rfin, alpha, omega);
+        if (ring) {
+            tile[buf][hslot] = mgfu_finish<T>(hfin, alpha, omega).x;
+            ctile[buf][hslot] = hfin.cd;
+        }
+        tile[buf][own] = cur.x;
+        ctile[buf][own] = cur.cd;
+        // own point: the CG update proper
+        if (valid) {
+            const int X = col + k * N2;
+            x[X] = x[X] + alpha * d[X];
+            rout[X] = cur.b;
+            const T z = cur.b * cur.inv;
+            acc[0] += (double)cur.b * (double)z;
+            acc[1] += (double)z * (double)z;
+        }
+        __syncthreads();
+        const T* tl = tile[buf];
+        const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
+        rsum += cur.b - mgf_apply<T, kMgFineShat>(v, cur.cd, ctile[buf][own + 1], ctile[buf][own + W], nxt.cd, 0, ft);
+        if (k & 1) {
+            const int cN = N >> 1;
+            T rs[1] = {rsum};
+            mg_pair_sum<T, 1>(rs, s.bxlog, pair_lds);
+            if (valid && !(gi & 1) && !(gj & 1)) bc[(gi >> 1) + cN * ((gj >> 1) + cN * (k >> 1))] = rs[0];
+            rsum = T(0);
+        }
+        xprev = cur.x;
+        cur = nxt;
+        buf ^= 1;
+    };
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+        plane(k, ra, rb, ha, hb);
+        plane(k + 1, rb, ra, hb, ha);
+    }
+    if (k < k1) plane(k, ra, rb, ha, hb);
     write_partials<2>(acc, part, kRZ, lb);
 }
 

@@ -153,6 +153,7 @@ struct stokes_ctx {
     // the SIMPLE matrix; about even for A, whose fused sweep loads z and d at
     // the ring points of three planes)
     int fuse_dir_A = 0, fuse_dir_S = 1;
+    int mg_pipe = 1;
     int mg_coarse_sweeps = 8;
     // coarse-level smoother: 0 damped Jacobi; 1 red-black Gauss-Seidel below the
     // tiled size; 2 red-black Gauss-Seidel on every coarse level but the coarsest
@@ -759,6 +760,9 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     if (kindA)
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
+    else if (c->mg_pipe && sizeof(T) == 8)
+        hipLaunchKernelGGL(k_mgf_smooth_S_pipe<T>, grid_of(s0), dim3(kBlock), 0, c->stream, s0, h.grid[1].n,
+                           c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
     else
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
@@ -786,7 +790,10 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
     T* bc = mg_view(c->mgS, 1, T()).b;
     const T omega = (T)c->mg_omega;
     const bool fuse = c->fuse_dir_S != 0;
-    auto body = [c, s, st, v, z, r2, d2, bc, omega, fuse](int parity) -> stokes_status {
+    // the software-pipelined level-0 sweeps gain in FP64 only (FP32 at 256^3:
+    // mixed solve 1.42 -> 1.43 s)
+    const bool pipe = c->mg_pipe != 0 && sizeof(T) == 8;
+    auto body = [c, s, st, v, z, r2, d2, bc, omega, fuse, pipe](int parity) -> stokes_status {
         T* rin = parity ? r2 : v.r;
         T* rout = parity ? v.r : r2;
         T* din = parity ? d2 : v.d;
@@ -794,8 +801,12 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
         bool open;
         if (fuse) {
             ST_TRY(time_begin(c, kTimeSDirStencil, &open));
-            hipLaunchKernelGGL(k_cgS_dirstencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
-                               (const T*)z, (const T*)din, dout, v.q, st, c->part);
+            if (pipe)
+                hipLaunchKernelGGL(k_cgS_dirstencil_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                                   (const T*)z, (const T*)din, dout, v.q, st, c->part);
+            else
+                hipLaunchKernelGGL(k_cgS_dirstencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                                   (const T*)z, (const T*)din, dout, v.q, st, c->part);
             ST_TRY(time_end(c, open));
         } else {
             // direction in place (pointwise), then the stencil
@@ -810,9 +821,14 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
             ST_TRY(time_end(c, open));
         }
         ST_TRY(time_begin(c, kTimeSUpdRestrict, &open));
-        hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineShat>), grid_of(s), dim3(kBlock), 0, c->stream, s,
-                           c->code, v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega, st,
-                           c->part);
+        if (pipe)
+            hipLaunchKernelGGL(k_mgf_update_restrict_S_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                               (const T*)v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega,
+                               st, c->part);
+        else
+            hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineShat>), grid_of(s), dim3(kBlock), 0, c->stream, s,
+                               c->code, v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega,
+                               st, c->part);
         ST_TRY(time_end(c, open));
         return vcycle<T>(c, c->mgS, rout, v.invd, z, st, true);
     };
@@ -1406,6 +1422,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "fuse_dir_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_A = (int)v; }
     else if (k == "fuse_dir_S") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_S = (int)v; }
+    else if (k == "mg_pipe") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->mg_pipe = (int)v; }
     else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }
     else return STOKES_E_ARG;
     return STOKES_OK;

@@ -489,6 +489,25 @@ def test_fused_direction_matches_separate_kernels(P):
         assert np.array_equal(val[3], ref[3]) and np.array_equal(val[4], ref[4]), key
 
 
+@pytest.mark.parametrize("N", [40, 64, 112])
+def test_pipelined_level0_sweeps_match_plain(P, N):
+    """The FP64 SIMPLE solve's level-0 sweeps with their loads issued a plane
+    ahead (option mg_pipe, default on) give bitwise the same solve as the plain
+    forms: 32-wide columns with two-plane runs (N = 40), 64-wide columns (64)
+    and 64-wide tiles running past the box edge (112)."""
+    m = spheres(N, 4.0, 0.45, 30 + N)
+    out = {}
+    with P.Stokes(m) as s:
+        for pipe in (1, 0):
+            s.set_option("mg_pipe", pipe)
+            r = s.solve(P.STOKES_SIMPLE, 1e-8)
+            p, u = s.fields()
+            out[pipe] = (r["k_hat"], r["outer_iters"], r["inner_A_iters"], r["inner_S_iters"], p, u)
+    say(f"    N={N}: k={out[1][0]:.15e} outer={out[1][1]} inner S={out[1][3]}")
+    assert out[1][:4] == out[0][:4]
+    assert np.array_equal(out[1][4], out[0][4]) and np.array_equal(out[1][5], out[0][5])
+
+
 @pytest.mark.parametrize("pc", ["simple", "uzawa"])
 def test_partial_wide_tiles_112(P, pc):
     """N = 112: 64-wide columns whose second tile runs past the box edge (wrapped
