@@ -1,6 +1,7 @@
-"""Write oracle_trajectories_64.json: the CPU oracle's outer CG trajectories on
-64^3 geometries, for GPU parity tests at a size the oracle needs about a
-minute per solve for (too slow to run inside the GPU test suite).
+"""Write oracle_trajectories_64.json (default) or oracle_trajectories_128.json
+(`--size 128`): the CPU oracle's outer CG trajectories on 64^3 geometries and on
+the 128^3 sphere pack r=6 porosity 0.5, for GPU parity tests at sizes the
+oracle needs minutes per solve for (too slow to run inside the GPU test suite).
 
 Calls only `oracle/` and the seeded input generators of `synth/`.  For each
 case the oracle solves twice, with inner tolerances 1e-12 (the GPU's) and
@@ -13,11 +14,12 @@ alpha, beta, k_hat and relative-residual columns up to the horizon, the
 extreme Ritz values of the tridiagonal built from those iterations and from
 all of them (Lanczos, Sec. 4.1.2), and a hash of the mask.
 
-    python tests/golden/make_oracle_trajectories.py
+    python tests/golden/make_oracle_trajectories.py [--size 128]
 """
 
 from __future__ import annotations
 
+import argparse
 import hashlib
 import json
 import os
@@ -34,14 +36,18 @@ if ROOT not in sys.path:
 import oracle  # noqa: E402
 from synth import grf, spheres  # noqa: E402
 
-OUT = os.path.join(HERE, "oracle_trajectories_64.json")
 HORIZON_RTOL = 1e-7
 
-CASES = [
-    # (name, generator call, preconditioners)
-    ("spheres N=64 r=4 phi=0.5 seed=11", lambda: spheres(64, 4.0, 0.5, 11), ("simple", "uzawa")),
-    ("grf N=64 corr=4 phi=0.35 seed=12", lambda: grf(64, 4.0, 0.35, 12), ("simple", "uzawa")),
-]
+CASES = {
+    64: [
+        # (name, generator call, preconditioners)
+        ("spheres N=64 r=4 phi=0.5 seed=11", lambda: spheres(64, 4.0, 0.5, 11), ("simple", "uzawa")),
+        ("grf N=64 corr=4 phi=0.35 seed=12", lambda: grf(64, 4.0, 0.35, 12), ("simple", "uzawa")),
+    ],
+    128: [
+        ("spheres N=128 r=6 phi=0.5 seed=0", lambda: spheres(128, 6.0, 0.5, 0), ("simple",)),
+    ],
+}
 
 
 def mask_hash(m):
@@ -60,10 +66,14 @@ def horizon(ha, hb):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--size", type=int, default=64, choices=sorted(CASES))
+    size = ap.parse_args().size
+    out_path = os.path.join(HERE, f"oracle_trajectories_{size}.json")
     out = {"source": "written by tests/golden/make_oracle_trajectories.py from the CPU oracle (FP64, Jacobi-PCG "
                      "inner solves); force (1, 0, 0), outer tol 1e-8 on ||r||/||r0||",
            "horizon_rtol": HORIZON_RTOL, "cases": []}
-    for name, gen, pcs in CASES:
+    for name, gen, pcs in CASES[size]:
         m = gen()
         o = oracle.Oracle(m, (1.0, 0.0, 0.0))
         for pc in pcs:
@@ -89,7 +99,7 @@ def main():
             out["cases"].append(case)
             print(f"{name} {pc}: outer {a['outer_iters']}/{b['outer_iters']} horizon {hz} "
                   f"k {a['k_hat']:.14e} ({time.perf_counter() - t0:.0f} s)", flush=True)
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
 
