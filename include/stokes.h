@@ -84,6 +84,7 @@ typedef enum {
 #define STOKES_FLAG_NO_FLOW        0x1u  /* no conducting fluid: k = 0 exactly */
 #define STOKES_FLAG_ZERO_RHS       0x2u  /* g = 0: the pressure is zero, no outer iteration */
 #define STOKES_FLAG_INNER_MAXIT    0x4u  /* an inner solve stopped at its iteration cap */
+#define STOKES_FLAG_MG_TWO_VISITS  0x8u  /* the SIMPLE matrix's multigrid cycle visited level 1 twice */
 
 typedef struct stokes_ctx stokes_ctx;
 
@@ -272,6 +273,15 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 with "mg_omega", like level 0
  *   "mg_level_blocks" workgroups a tiled coarse-level sweep aims for (levels
  *                 with a side of 64 or more; default 1024)
+ *   "mg_visits"   visits of level 1 per cycle of the SIMPLE matrix.  Two
+ *                 visits: after the first visit's result y_1, a second cycle
+ *                 from level 1 down on the residual b_1 - A_1 y_1, its result
+ *                 added to y_1 (the cycle stays linear and symmetric); only
+ *                 where level 1 has a side of at least 64, is not the coarsest
+ *                 and runs damped Jacobi ("mg_coarse_gs" not 2).  0 (default):
+ *                 two visits where level 1 has a side of at least 128 (boxes
+ *                 of 256 and more); 1: always one (the plain V-cycle); 2: two
+ *                 wherever allowed.
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

@@ -45,6 +45,7 @@ from .stokes import (  # noqa: F401
     STOKES_FLAG_NO_FLOW,
     STOKES_FLAG_ZERO_RHS,
     STOKES_FLAG_INNER_MAXIT,
+    STOKES_FLAG_MG_TWO_VISITS,
     STOKES_OK,
     STOKES_NOT_CONVERGED,
     STOKES_E_ARG,

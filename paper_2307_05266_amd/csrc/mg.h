@@ -1096,18 +1096,26 @@ __global__ void __launch_bounds__(kGsThreads) k_mgc_gs_postsmooth(MgGrid g, MgOp
 }
 
 // Levels >= 1 with a side of at least 64, LDS-tiled like level 0: the
-// smoothed iterate (x0 = omega D^-1 b, plus scale P xc when smoothing) once per
-// point, own column k-1, k, k+1 in registers, plane k plus a ring in LDS.  The
-// couplings to +x and +y are read from the neighbour's W^x, W^y; the one to +z
-// is the next plane's own W^z.  s: a sweep over this level (even z-runs).
+// iterate x once per point, own column k-1, k, k+1 in registers, plane k plus a
+// ring in LDS.  The couplings to +x and +y are read from the neighbour's W^x,
+// W^y; the one to +z is the next plane's own W^z.  s: a sweep over this level
+// (even z-runs).  MODE:
+//   kMgcPre      x = omega D^-1 b; the residual b - A x summed over 2x2x2 into out (level + 1)
+//   kMgcPost     x = omega D^-1 b + scale P xc; out = x + omega D^-1 (b - A x)
+//   kMgcPostAcc  as kMgcPost, added to what out holds (the second of two visits)
+//   kMgcResid    x = xc (an iterate of this level); out = b - A x
+// Nodes that are not unknowns (D = 0) get 0 in the post and residual forms.
+constexpr int kMgcPre = 0, kMgcPost = 1, kMgcPostAcc = 2, kMgcResid = 3;
+
 template <class T, int NB>
 struct MgcPt {
     T d[NB], b[NB], x[NB], wz[NB];
 };
 
-template <class T, int NB, bool POST>
+template <class T, int NB, int MODE>
 __device__ __forceinline__ void mgc_point(MgcPt<T, NB>& q, int n, int cn, int i, int j, int k, const MgOp& op,
                                           const T* __restrict__ b, const T* __restrict__ xc, T scale, T omega) {
+    constexpr bool POST = MODE == kMgcPost || MODE == kMgcPostAcc;
     const size_t n3 = (size_t)n * n * n;
     const int X = i + n * (j + n * k);
     const T* D = (const T*)op.D;
@@ -1119,6 +1127,10 @@ __device__ __forceinline__ void mgc_point(MgcPt<T, NB>& q, int n, int cn, int i,
 #pragma unroll
         for (int a = 0; a < NB; ++a) e[a] = xc[a * cn3 + C];
     }
+    if (MODE == kMgcResid) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) e[a] = xc[a * n3 + X];
+    }
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
         q.d[a] = D[a * n3 + X];
@@ -1127,21 +1139,26 @@ __device__ __forceinline__ void mgc_point(MgcPt<T, NB>& q, int n, int cn, int i,
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-        const T inv = q.d[a] > T(0) ? T(1) / q.d[a] : T(0);
-        q.x[a] = omega * inv * q.b[a];
-        if (POST) q.x[a] += scale * e[a];
+        if (MODE == kMgcResid) {
+            q.x[a] = e[a];
+        } else {
+            const T inv = q.d[a] > T(0) ? T(1) / q.d[a] : T(0);
+            q.x[a] = omega * inv * q.b[a];
+            if (POST) q.x[a] += scale * e[a];
+        }
     }
 }
 
-template <class T, int NB, bool POST>
+template <class T, int NB, int MODE>
 __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, const T* __restrict__ b,
                                                       const T* __restrict__ xc, T scale, T omega, T* __restrict__ out,
                                                       const CgState* st) {
+    constexpr bool PRE = MODE == kMgcPre;
     shift_nn((size_t)blockIdx.y * s.bstride, b, out);
     shift_all((size_t)blockIdx.y * s.bstride, xc, st);
     shift_op(op, (size_t)blockIdx.y * s.bstride);
     __shared__ T tile[2][NB][kTileMax];
-    __shared__ T pair_lds[POST ? 1 : NB * kBlock / 2];
+    __shared__ T pair_lds[PRE ? NB * kBlock / 2 : 1];
     const Tile t = tile_of(s);
     const int n = t.N, W = t.W;
     const size_t n3 = (size_t)s.n3;
@@ -1152,11 +1169,11 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
     T xprev[NB];
     {
         MgcPt<T, NB> pv;
-        mgc_point<T, NB, POST>(pv, n, cn, t.wi, t.wj, zw(t.k0 - 1), op, b, xc, scale, omega);
+        mgc_point<T, NB, MODE>(pv, n, cn, t.wi, t.wj, zw(t.k0 - 1), op, b, xc, scale, omega);
 #pragma unroll
         for (int a = 0; a < NB; ++a) xprev[a] = pv.x[a];
     }
-    mgc_point<T, NB, POST>(cur, n, cn, t.wi, t.wj, t.k0, op, b, xc, scale, omega);
+    mgc_point<T, NB, MODE>(cur, n, cn, t.wi, t.wj, t.k0, op, b, xc, scale, omega);
     // a finished solve is checked after the first loads (in bounds either way)
     if (st && st->done) return;
     T rsum[NB];
@@ -1165,10 +1182,10 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
     const int xp = t.wi == n - 1 ? 0 : t.wi + 1, yp = t.wj == n - 1 ? 0 : t.wj + 1;
     int buf = 0;
     for (int k = t.k0; k < t.k1; ++k) {
-        mgc_point<T, NB, POST>(nxt, n, cn, t.wi, t.wj, zw(k + 1), op, b, xc, scale, omega);
+        mgc_point<T, NB, MODE>(nxt, n, cn, t.wi, t.wj, zw(k + 1), op, b, xc, scale, omega);
         if (t.ring) {
             MgcPt<T, NB> hp;
-            mgc_point<T, NB, POST>(hp, n, cn, t.hi, t.hj, k, op, b, xc, scale, omega);
+            mgc_point<T, NB, MODE>(hp, n, cn, t.hi, t.hj, k, op, b, xc, scale, omega);
 #pragma unroll
             for (int a = 0; a < NB; ++a) tile[buf][a][t.hslot] = hp.x[a];
         }
@@ -1191,14 +1208,19 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
             const T ax = cur.d[a] * cur.x[a] - (((wx[a] * tl[t.own - 1] + wxp[a] * tl[t.own + 1]) +
                                                  (wy[a] * tl[t.own - W] + wyp[a] * tl[t.own + W])) +
                                                 (cur.wz[a] * xprev[a] + nxt.wz[a] * nxt.x[a]));
-            if (POST) {
+            if (MODE == kMgcPost || MODE == kMgcPostAcc) {
                 const T inv = cur.d[a] > T(0) ? T(1) / cur.d[a] : T(0);
-                if (t.valid) out[a * n3 + X] = inv > T(0) ? cur.x[a] + omega * inv * (cur.b[a] - ax) : T(0);
+                if (t.valid) {
+                    const T y = inv > T(0) ? cur.x[a] + omega * inv * (cur.b[a] - ax) : T(0);
+                    out[a * n3 + X] = MODE == kMgcPostAcc ? out[a * n3 + X] + y : y;
+                }
+            } else if (MODE == kMgcResid) {
+                if (t.valid) out[a * n3 + X] = cur.d[a] > T(0) ? cur.b[a] - ax : T(0);
             } else {
                 rsum[a] += cur.b[a] - ax;
             }
         }
-        if (!POST && (k & 1)) {
+        if (PRE && (k & 1)) {
             mg_pair_sum<T, NB>(rsum, s.bxlog, pair_lds);
             const size_t cn3 = (size_t)cn * cn * cn;
 #pragma unroll

@@ -134,8 +134,9 @@ struct stokes_ctx {
         int nb = 1, kind = 0;
         std::vector<MgGrid> grid;      // [0..levels]
         std::vector<Sweep> sweep;      // [0..levels]: sweeps of the tiled level kernels (side >= 64)
-        struct Lev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y; };
-        struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y; };
+        // w: level 1 only, the residual of the first visit of a two-visit cycle
+        struct Lev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y, *w; };
+        struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y, *w; };
         std::vector<Lev64> l64;        // [1..levels]
         std::vector<Lev32> l32;
         double* z = nullptr;           // fine level: output of the cycle
@@ -159,6 +160,12 @@ struct stokes_ctx {
     // tiled size; 2 red-black Gauss-Seidel on every coarse level but the coarsest
     int mg_coarse_gs = 1;
     int mg_level_blocks = kMgLevelBlocksDefault;   // target blocks of a tiled coarse-level sweep
+    // visits of level 1 per cycle of the SIMPLE matrix: 0 (auto) two where level
+    // 1 has a side of at least kMgTwoVisitMinSide, 1 never, 2 wherever level 1 is
+    // tiled; never where level 1 is the coarsest or smooths by Gauss-Seidel
+    int mg_visits = 0;
+    int mg_two_ok = 0;             // auto mode: 0 not yet estimated, 1 two visits, -1 one
+    double mg_lambda1 = 0.0;       // the estimate of the largest eigenvalue of B_1 A_1
     CgState* cg = nullptr;         // [0] A, [1] SIMPLE
     double* part = nullptr;        // [kNumSlots][kMaxBlocks] partials of the inner loops
     double* dpart = nullptr;       // [kMaxBlocks][3] partials of host-side sums
@@ -611,6 +618,7 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
         auto& lv = h.l64[l];
         const size_t m = (size_t)nb * h.grid[l].n3;
         for (double** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, m));
+        if (l == 1) ST_TRY(dev_alloc(c, &lv.w, m));
     }
     ST_TRY(dev_alloc(c, &h.z, (size_t)nb * c->n3));
     ST_TRY(dev_alloc(c, &h.r2, (size_t)nb * c->n3));
@@ -639,6 +647,7 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
         auto& lv = h.l32[l];
         const int m = h.nb * h.grid[l].n3;
         for (float** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, (size_t)m));
+        if (l == 1) ST_TRY(dev_alloc(c, &lv.w, (size_t)m));
         const auto& d = h.l64[l];
         const double* src[4] = {d.D, d.Wx, d.Wy, d.Wz};
         float* dst[4] = {lv.D, lv.Wx, lv.Wy, lv.Wz};
@@ -655,15 +664,15 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
 
 template <class T>
 struct MgView {
-    T *D, *Wx, *Wy, *Wz, *b, *x, *y;
+    T *D, *Wx, *Wy, *Wz, *b, *x, *y, *w;
 };
 MgView<double> mg_view(MgHier& h, int l, double) {
     auto& v = h.l64[l];
-    return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y};
+    return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y, v.w};
 }
 MgView<float> mg_view(MgHier& h, int l, float) {
     auto& v = h.l32[l];
-    return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y};
+    return {v.D, v.Wx, v.Wy, v.Wz, v.b, v.x, v.y, v.w};
 }
 double* mg_out(MgHier& h, double) { return h.z; }
 float* mg_out(MgHier& h, float) { return h.z32; }
@@ -672,16 +681,32 @@ float* mg_r2(MgHier& h, float) { return h.r2_32; }
 double* mg_d2(MgHier& h, double) { return h.d2; }
 float* mg_d2(MgHier& h, float) { return h.d2_32; }
 
-// z0 = V-cycle applied to the fine residual b0; the last fine sweep writes the
-// partials of (b0, z0) into the RZ slot of the CG loop (grid = the CG sweeps').
+// The SIMPLE matrix's cycle visits level 1 twice where level 1 runs the tiled
+// Jacobi kernels (a side of at least 64) and is not the coarsest, by default
+// from a level-1 side of kMgTwoVisitMinSide: the second visit costs the
+// latency-bound launches of the levels below 1 (about constant) and saves a
+// third of the iterations on tight geometries, which pays where the level-0
+// sweeps are long (measured: 256^3 tight spheres, FP64 solve 5.65 -> 4.74 s;
+// 128^3 spheres, 1.01 -> 1.11 s).
+// The auto mode also needs the estimate of prepare_two_visits below.
+constexpr int kMgTwoVisitMinSide = 128;
+bool mg_two_visits_allowed(const stokes_ctx* c, const MgHier& h) {
+    return c->mg_visits != 1 && h.kind != kMgFineA && h.levels >= 2 && h.grid[1].n >= kMgTiledMinSide &&
+           c->mg_coarse_gs != 2;
+}
+bool mg_two_visits(const stokes_ctx* c, const MgHier& h) {
+    if (!mg_two_visits_allowed(c, h)) return false;
+    return c->mg_visits == 2 || (h.grid[1].n >= kMgTwoVisitMinSide && c->mg_two_ok == 1);
+}
+
+// The coarse levels from..L of a cycle: the cycle on b_from (the right-hand
+// side of level `from`), its result in y_from (the coarsest level's in its x);
+// acc: added to y_from (a tiled level only).
 template <class T>
-stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st,
-                     bool restricted = false) {
+stokes_status mg_coarse(stokes_ctx* c, MgHier& h, int from, const T* bfrom, bool acc, const CgState* st) {
     const int L = h.levels;
-    const Sweep& s0 = inner_sweep(c, T());   // level 0: the inner solve's sweep
     const T omega = (T)c->mg_omega, scale = (T)(h.kind == kMgFineA ? c->mg_scale_A : c->mg_scale);
     std::vector<MgOp> ops(L + 1);
-    ops[0] = {c->code, h.kind, invd0, nullptr, nullptr, nullptr, nullptr};
     for (int l = 1; l <= L; ++l) {
         auto v = mg_view(h, l, T());
         ops[l] = {nullptr, 0, nullptr, v.D, v.Wx, v.Wy, v.Wz};
@@ -693,6 +718,83 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
         const int n = h.grid[l].n;
         return n >= kGsMinSide && (c->mg_coarse_gs == 2 || (c->mg_coarse_gs == 1 && n < kMgTiledMinSide));
     };
+    // level l (1 <= l < L) going down: smooth on b_l from zero, restrict the residual into level l+1
+    auto pre = [&](int l, const T* bl) {
+        T* bn = mg_view(h, l + 1, T()).b;
+        if (use_gs(l)) {
+            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
+        } else if (h.grid[l].n >= kMgTiledMinSide) {
+            const Sweep& ls = h.sweep[l];
+            if (kindA)
+                hipLaunchKernelGGL((k_mgc_tiled<T, 3, kMgcPre>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
+            else
+                hipLaunchKernelGGL((k_mgc_tiled<T, 1, kMgcPre>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
+        } else {
+            hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1)), c->nbatch), dim3(kBlock), 0,
+                               c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
+        }
+    };
+    // the result of level l is in its y (the coarsest level's in its x)
+    auto coarse_x = [&](int l) -> const T* { return l == L ? mg_view(h, L, T()).x : mg_view(h, l, T()).y; };
+    // level l going up: prolong the correction of level l+1 and postsmooth on b_l into y_l
+    // (acc: added to y_l; tiled levels only)
+    auto post = [&](int l, const T* bl, bool acc) {
+        T* y = mg_view(h, l, T()).y;
+        if (use_gs(l)) {
+            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
+                               h.grid[l], ops[l], bl, coarse_x(l + 1), h.grid[l + 1].n, scale, y, st);
+        } else if (h.grid[l].n >= kMgTiledMinSide) {
+            const Sweep& ls = h.sweep[l];
+            if (kindA)
+                hipLaunchKernelGGL((k_mgc_tiled<T, 3, kMgcPost>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, coarse_x(l + 1), scale, omega, y, st);
+            else if (acc)
+                hipLaunchKernelGGL((k_mgc_tiled<T, 1, kMgcPostAcc>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, coarse_x(l + 1), scale, omega, y, st);
+            else
+                hipLaunchKernelGGL((k_mgc_tiled<T, 1, kMgcPost>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
+                                   h.grid[l + 1].n, ops[l], bl, coarse_x(l + 1), scale, omega, y, st);
+        } else {
+            hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l)), c->nbatch), dim3(kBlock), 0, c->stream,
+                               h.grid[l], ops[l], bl, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, y, st);
+        }
+    };
+    // levels from .. L: the cycle on b_from, result in y_from (acc: added to it)
+    auto subcycle = [&](int from, const T* bfrom, bool acc) {
+        for (int l = from; l < L; ++l) pre(l, l == from ? bfrom : mg_view(h, l, T()).b);
+        auto v = mg_view(h, L, T());
+        // coarsest: Jacobi sweeps in one workgroup, result in x
+        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1, c->nbatch), dim3(kMgCoarsestThreads), 0, c->stream, h.grid[L], ops[L],
+                           (const T*)v.b, v.x, omega, c->mg_coarse_sweeps, st);
+        for (int l = L - 1; l >= from; --l)
+            post(l, l == from ? bfrom : mg_view(h, l, T()).b, acc && l == from);
+    };
+    subcycle(from, bfrom, acc);
+    HIP_TRY(hipGetLastError());
+    return STOKES_OK;
+}
+
+// w_1 = b_1 - A_1 y_1 on level 1 of a hierarchy (tiled level 1)
+template <class T>
+void mg_level1_residual(stokes_ctx* c, MgHier& h, const T* b1, const T* y1, T* w1, const CgState* st) {
+    auto v1 = mg_view(h, 1, T());
+    const MgOp op1 = {nullptr, 0, nullptr, v1.D, v1.Wx, v1.Wy, v1.Wz};
+    const Sweep& ls = h.sweep[1];
+    hipLaunchKernelGGL((k_mgc_tiled<T, 1, kMgcResid>), grid_of(ls), dim3(kBlock), 0, c->stream, ls, h.grid[2].n, op1,
+                       b1, y1, T(0), (T)c->mg_omega, w1, st);
+}
+
+// z0 = V-cycle applied to the fine residual b0; the last fine sweep writes the
+// partials of (b0, z0) into the RZ slot of the CG loop (grid = the CG sweeps').
+template <class T>
+stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z0, const CgState* st,
+                     bool restricted = false) {
+    const Sweep& s0 = inner_sweep(c, T());   // level 0: the inner solve's sweep
+    const T omega = (T)c->mg_omega, scale = (T)(h.kind == kMgFineA ? c->mg_scale_A : c->mg_scale);
+    const bool kindA = h.kind == kMgFineA;
     // descend: residual of the first Jacobi sweep, restricted (unless the
     // fused CG update already did)
     if (!restricted) {
@@ -708,66 +810,92 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
                                s0, cg.n, c->code, invd0, b0, (const T*)nullptr, T(0), omega, bc, nullptr, 0, st);
         ST_TRY(time_end(c, open));
     }
-    for (int l = 1; l < L; ++l) {
-        const T* bl = mg_view(h, l, T()).b;
-        T* bn = mg_view(h, l + 1, T()).b;
-        if (use_gs(l)) {
-            hipLaunchKernelGGL(k_mgc_gs_restrict<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
-                               h.grid[l], h.grid[l + 1], ops[l], bl, bn, st);
-        } else if (h.grid[l].n >= kMgTiledMinSide) {
-            const Sweep& ls = h.sweep[l];
-            if (kindA)
-                hipLaunchKernelGGL((k_mgc_tiled<T, 3, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
-                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
-            else
-                hipLaunchKernelGGL((k_mgc_tiled<T, 1, false>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
-                                   h.grid[l + 1].n, ops[l], bl, (const T*)nullptr, T(0), omega, bn, st);
-        } else {
-            hipLaunchKernelGGL(k_mgc_restrict<T>, dim3(exact_blocks(8 * (int64_t)nodes(l + 1)), c->nbatch), dim3(kBlock), 0,
-                               c->stream, h.grid[l], h.grid[l + 1], ops[l], bl, bn, omega, st);
-        }
+    ST_TRY(mg_coarse<T>(c, h, 1, (const T*)mg_view(h, 1, T()).b, false, st));
+    // Two visits of level 1 (the SIMPLE matrix; see mg_two_visits): the second
+    // cycles on the residual the first leaves, w = b_1 - A_1 y_1, and adds its
+    // result to y_1.  Linear and symmetric, so the inner CG stays standard.
+    if (mg_two_visits(c, h)) {
+        auto v1 = mg_view(h, 1, T());
+        mg_level1_residual<T>(c, h, v1.b, v1.y, v1.w, st);
+        ST_TRY(mg_coarse<T>(c, h, 1, (const T*)v1.w, true, st));
     }
-    // coarsest: Jacobi sweeps in one workgroup, result in x
-    {
-        auto v = mg_view(h, L, T());
-        hipLaunchKernelGGL(k_mg_coarsest<T>, dim3(1, c->nbatch), dim3(kMgCoarsestThreads), 0, c->stream, h.grid[L], ops[L],
-                           (const T*)v.b, v.x, omega, c->mg_coarse_sweeps, st);
-    }
-    // ascend: prolong the correction and postsmooth; the result of level l is
-    // in its y (level 0: z0)
-    auto coarse_x = [&](int l) -> const T* { return l == L ? mg_view(h, L, T()).x : mg_view(h, l, T()).y; };
-    for (int l = L - 1; l >= 1; --l) {
-        auto v = mg_view(h, l, T());
-        if (use_gs(l)) {
-            hipLaunchKernelGGL(k_mgc_gs_postsmooth<T>, dim3(gs_blocks(h.grid[l]), c->nbatch), dim3(kGsThreads), 0, c->stream,
-                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, v.y, st);
-        } else if (h.grid[l].n >= kMgTiledMinSide) {
-            const Sweep& ls = h.sweep[l];
-            if (kindA)
-                hipLaunchKernelGGL((k_mgc_tiled<T, 3, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
-                                   h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
-            else
-                hipLaunchKernelGGL((k_mgc_tiled<T, 1, true>), grid_of(ls), dim3(kBlock), 0, c->stream, ls,
-                                   h.grid[l + 1].n, ops[l], (const T*)v.b, coarse_x(l + 1), scale, omega, v.y, st);
-        } else {
-            hipLaunchKernelGGL(k_mgc_postsmooth<T>, dim3(exact_blocks(nodes(l)), c->nbatch), dim3(kBlock), 0, c->stream,
-                               h.grid[l], ops[l], (const T*)v.b, coarse_x(l + 1), h.grid[l + 1].n, scale, omega, v.y,
-                               st);
-        }
-    }
+    const T* xc1 = h.levels == 1 ? mg_view(h, 1, T()).x : mg_view(h, 1, T()).y;
     bool open;
     ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : kTimeMgSSmooth, &open));
     if (kindA)
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
-                           h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
+                           h.grid[1].n, c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
     else if (c->mg_pipe && sizeof(T) == 8)
         hipLaunchKernelGGL(k_mgf_smooth_S_pipe<T>, grid_of(s0), dim3(kBlock), 0, c->stream, s0, h.grid[1].n,
-                           c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
+                           c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
     else
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
-                           h.grid[1].n, c->code, invd0, b0, coarse_x(1), scale, omega, z0, c->part, kRZ, st);
+                           h.grid[1].n, c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
     ST_TRY(time_end(c, open));
     HIP_TRY(hipGetLastError());
+    return STOKES_OK;
+}
+
+// Two visits of level 1 act on level 1 as 2 B_1 - B_1 A_1 B_1 (B_1: the cycle
+// from level 1 down), whose eigenvalues relative to A_1 are 1 - (1 - mu)^2 for
+// the eigenvalues mu of B_1 A_1: positive only while mu < 2.  The over-corrected
+// coarse corrections push mu above 1, the more so the deeper the hierarchy below
+// level 1 (CPU model, random-field packs: 1.40 with three levels below level 1,
+// 1.73 with four).  So in the auto mode the largest mu is estimated once per
+// context (again after a multigrid option changes) by power iteration on the
+// device with host dot products, and two visits are used only below
+// kMgTwoVisitMaxLambda.  Plain contexts only (batched ones keep one visit).
+constexpr double kMgTwoVisitMaxLambda = 1.8;
+constexpr int kMgTwoVisitPowerIts = 20;
+
+stokes_status prepare_two_visits(stokes_ctx* c) {
+    MgHier& h = c->mgS;
+    if (c->mg_two_ok != 0) return STOKES_OK;
+    c->mg_two_ok = -1;
+    if (c->mg_visits != 0 || !c->use_mg || !mg_two_visits_allowed(c, h) || h.grid[1].n < kMgTwoVisitMinSide ||
+        c->nbatch != 1)
+        return STOKES_OK;
+    auto v1 = mg_view(h, 1, 0.0);
+    const size_t n1 = (size_t)h.grid[1].n3;
+    std::vector<double> D(n1), x(n1), ax(n1), y(n1);
+    HIP_TRY(hipMemcpyAsync(D.data(), v1.D, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemsetAsync(v1.x, 0, n1 * sizeof(double), c->stream));   // zero right-hand side of the residual
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    uint64_t seed = 0x9E3779B97F4A7C15ull;
+    for (size_t i = 0; i < n1; ++i) {
+        seed ^= seed << 13;
+        seed ^= seed >> 7;
+        seed ^= seed << 17;
+        x[i] = D[i] > 0.0 ? (double)(seed >> 11) * 0x1.0p-53 - 0.5 : 0.0;
+    }
+    double mu = 0.0;
+    for (int it = 0; it < kMgTwoVisitPowerIts; ++it) {
+        HIP_TRY(hipMemcpyAsync(v1.w, x.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        mg_level1_residual<double>(c, h, v1.x, v1.w, v1.b, nullptr);   // b_1 = 0 - A_1 x
+        ST_TRY(mg_coarse<double>(c, h, 1, (const double*)v1.b, false, nullptr));   // y_1 = B_1 b_1
+        HIP_TRY(hipMemcpyAsync(ax.data(), v1.b, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(y.data(), v1.y, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        // signs cancel: (A x, B A x) / (A x, x) from b_1 = -A x and y_1 = -B A x
+        double num = 0.0, den = 0.0, yy = 0.0;
+        for (size_t i = 0; i < n1; ++i) {
+            num += ax[i] * y[i];
+            den += ax[i] * x[i];
+            yy += y[i] * y[i];
+        }
+        den = -den;
+        if (!(den > 0.0) || !(yy > 0.0) || !std::isfinite(num)) return STOKES_OK;   // nothing to estimate
+        mu = num / den;
+        const double sc = -1.0 / std::sqrt(yy);
+        for (size_t i = 0; i < n1; ++i) x[i] = y[i] * sc;
+    }
+    c->mg_lambda1 = mu;
+    c->mg_two_ok = mu < kMgTwoVisitMaxLambda ? 1 : -1;
+    if (c->progress > 0) {
+        std::fprintf(stderr, "[stokes] N=%d largest eigenvalue of B_1 A_1 ~ %.4f: %s visit%s of level 1\n", c->N, mu,
+                     c->mg_two_ok == 1 ? "two" : "one", c->mg_two_ok == 1 ? "s" : "");
+        std::fflush(stderr);
+    }
     return STOKES_OK;
 }
 
@@ -1332,7 +1460,7 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
         if (ns.size() < 2) continue;
         for (int prec = 0; prec <= precision; ++prec) {
             const int64_t w = prec == 0 ? 8 : 4;
-            for (size_t l = 1; l < ns.size(); ++l) t += 7 * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
+            for (size_t l = 1; l < ns.size(); ++l) t += (l == 1 ? 8 : 7) * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
             t += 3 * blk(nb * n3, w);   // cycle output, second residual and direction on level 0
         }
     }
@@ -1374,6 +1502,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     const std::string k(key);
     // captured iterations bake in launch shapes and multigrid parameters
     drop_graphs(c);
+    if (k.compare(0, 2, "mg") == 0) c->mg_two_ok = 0;   // the two-visit estimate depends on the cycle
     if (k == "eps_A") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_A = v; }
     else if (k == "eps_S") { if (!(v > 0.0 && v < 1.0)) return STOKES_E_ARG; c->eps_S = v; }
     else if (k == "max_outer") { if (v < 1 || v > 1e7) return STOKES_E_ARG; c->max_outer = (int)v; }
@@ -1422,6 +1551,7 @@ stokes_status stokes_set_option(stokes_ctx* c, const char* key, double v) {
     else if (k == "progress") { if (v < 0 || v > 1e7 || v != std::floor(v)) return STOKES_E_ARG; c->progress = (int)v; }
     else if (k == "fuse_dir_A") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_A = (int)v; }
     else if (k == "fuse_dir_S") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->fuse_dir_S = (int)v; }
+    else if (k == "mg_visits") { if (v != 0.0 && v != 1.0 && v != 2.0) return STOKES_E_ARG; c->mg_visits = (int)v; }
     else if (k == "mg_pipe") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->mg_pipe = (int)v; }
     else if (k == "graphs") { if (v != 0.0 && v != 1.0) return STOKES_E_ARG; c->use_graphs = (int)v; }
     else return STOKES_E_ARG;
@@ -1991,6 +2121,7 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     if (!c) return STOKES_E_ARG;
     if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
     if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
+    ST_TRY(prepare_two_visits(c));
     const auto t0 = std::chrono::steady_clock::now();
     c->t_solve0 = t0;
     stokes_status st;
@@ -2003,6 +2134,10 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     c->rep.seconds = secs;
     for (auto& r : c->mrep) r.seconds = secs;
+    if (precond == STOKES_SIMPLE && c->use_mg && mg_two_visits(c, c->mgS)) {
+        c->rep.flags |= STOKES_FLAG_MG_TWO_VISITS;
+        for (auto& r : c->mrep) r.flags |= STOKES_FLAG_MG_TWO_VISITS;
+    }
     if (report) *report = c->rep;
     return st;
 }
@@ -2013,6 +2148,7 @@ stokes_status stokes_solve_rhs(stokes_ctx* c, stokes_precond precond, double tol
     if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
     if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
     if (c->batch_api || c->precision != 0) return STOKES_E_STATE;
+    ST_TRY(prepare_two_visits(c));
     const auto t0 = std::chrono::steady_clock::now();
     c->t_solve0 = t0;
     stokes_status st;
@@ -2022,6 +2158,7 @@ stokes_status stokes_solve_rhs(stokes_ctx* c, stokes_precond precond, double tol
         st = STOKES_E_NOMEM;
     }
     c->rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (precond == STOKES_SIMPLE && c->use_mg && mg_two_visits(c, c->mgS)) c->rep.flags |= STOKES_FLAG_MG_TWO_VISITS;
     if (report) *report = c->rep;
     return st;
 }
@@ -2083,6 +2220,7 @@ static stokes_status apply_impl(stokes_ctx* c, int op, const double* in, double*
     const bool face_in = op == STOKES_OP_A || op == STOKES_OP_B || op == STOKES_OP_MG_A;
     const bool face_out = op == STOKES_OP_A || op == STOKES_OP_BT || op == STOKES_OP_DIAG_A || op == STOKES_OP_MG_A;
     const bool no_in = op == STOKES_OP_DIAG_A || op == STOKES_OP_DIAG_SHAT;
+    if (op == STOKES_OP_MG_SHAT) ST_TRY(prepare_two_visits(c));
     double* src = face_in ? c->fd : c->sd;
     double* dst = face_out ? c->fq : c->sq;
     if (!no_in) {

@@ -25,7 +25,7 @@ STOKES_UZAWA, STOKES_SIMPLE = 0, 1
 (STOKES_OP_A, STOKES_OP_B, STOKES_OP_BT, STOKES_OP_SHAT, STOKES_OP_DIAG_A, STOKES_OP_DIAG_SHAT,
  STOKES_OP_PROJECT, STOKES_OP_S, STOKES_OP_MG_SHAT, STOKES_OP_MG_A) = range(10)
 STOKES_KEEP_ALL_COMPONENTS = 0x1
-STOKES_FLAG_NO_FLOW, STOKES_FLAG_ZERO_RHS, STOKES_FLAG_INNER_MAXIT = 0x1, 0x2, 0x4
+STOKES_FLAG_NO_FLOW, STOKES_FLAG_ZERO_RHS, STOKES_FLAG_INNER_MAXIT, STOKES_FLAG_MG_TWO_VISITS = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "stokes_setup", "stokes_setup_ex", "stokes_set_stream", "stokes_set_option", "stokes_solve",

@@ -7,7 +7,11 @@ Galerkin coarse operators, damped Jacobi (0.9) on level 0 and on the coarse
 levels with a side of 64 or more, red-black Gauss-Seidel (red then black
 going down, black then red going up) on the smaller coarse levels, 8
 damped-Jacobi sweeps from zero on the coarsest level, the coarse correction
-scaled by 1.7 (SIMPLE matrix) or 1.5 (A): the library's defaults.  The cycle
+scaled by 1.7 (SIMPLE matrix) or 1.5 (A): the library's defaults.  For the
+SIMPLE matrix, level 1 is visited twice (the second visit on the residual the
+first leaves, its result added to the first's) where level 1 is tiled and not
+the coarsest: by default from a level-1 side of 128, with option mg_visits=2
+from 64, which the 128^3 cases use.  The cycle
 is the preconditioner the library gives the role of the paper's algebraic
 multigrid (Sec. 3.2); the paper does not define it, so the model pins the
 implementation, not a formula of the paper.
@@ -86,7 +90,15 @@ def relax(A, inv, x, b, mask):
     return y
 
 
-def cycle(levels, Ps, b, gs, scale, l=0):
+def two_visits(levels, gs, visits):
+    """The SIMPLE matrix's cycle visits level 1 twice where level 1 runs the tiled
+    Jacobi smoother (side >= 64, not Gauss-Seidel) and is not the coarsest: with
+    option mg_visits 2 always, with 0 (the default) from a level-1 side of 128."""
+    allowed = len(levels) >= 3 and levels[1][0] >= TILED_MIN_SIDE and gs != 2
+    return allowed and (visits == 2 or (visits == 0 and levels[1][0] >= 128))
+
+
+def cycle(levels, Ps, b, gs, scale, l=0, visits=1):
     n, A, inv = levels[l]
     L = len(levels) - 1
     if l == L:
@@ -102,7 +114,13 @@ def cycle(levels, Ps, b, gs, scale, l=0):
         x = relax(A, inv, x, b, blk)
     else:
         x = OMEGA * inv * b
-    xc = cycle(levels, Ps, Ps[l].T @ (b - A @ x), gs, scale, l + 1)
+    bc = Ps[l].T @ (b - A @ x)
+    xc = cycle(levels, Ps, bc, gs, scale, l + 1)
+    if l == 0 and visits == 2:
+        # second visit of level 1 on the residual the first leaves, added to its result
+        _, Ac, invc = levels[1]
+        w = np.where(invc > 0, bc - Ac @ xc, 0.0)
+        xc = xc + cycle(levels, Ps, w, gs, scale, 1)
     x = x + scale * (Ps[l] @ xc)
     if use_gs:
         x = relax(A, inv, x, b, blk)
@@ -117,11 +135,12 @@ def embed(M, pos, n3):
     return (E @ M @ E.T).tocsr()
 
 
-CASES = [(36, 2, 1), (48, 5, 1), (128, 0, 1), (36, 2, 0), (48, 5, 0), (128, 0, 0), (128, 0, 2)]
+CASES = [(36, 2, 1, 0), (48, 5, 1, 0), (128, 0, 1, 0), (36, 2, 0, 2), (48, 5, 0, 2), (128, 0, 0, 2), (128, 0, 2, 2),
+         (128, 0, 1, 2)]
 
 
-@pytest.mark.parametrize("N,seed,gs", CASES)
-def test_vcycle_matches_model(P, N, seed, gs):
+@pytest.mark.parametrize("N,seed,gs,visits", CASES)
+def test_vcycle_matches_model(P, N, seed, gs, visits):
     m = spheres(N, 3.0 if N < 128 else 6.0, 0.45 if N < 128 else 0.5, seed)
     o = oracle.Oracle(m)
     n3 = N ** 3
@@ -139,6 +158,7 @@ def test_vcycle_matches_model(P, N, seed, gs):
     nsA = mg_plan(N, 3)
     with P.Stokes(m) as s:
         s.set_option("mg_coarse_gs", gs)
+        s.set_option("mg_visits", visits)
         info = s.info()
         z = s.apply(P.STOKES_OP_MG_SHAT, b).reshape(-1)
         if len(nsA) > 1:
@@ -149,9 +169,10 @@ def test_vcycle_matches_model(P, N, seed, gs):
                 s.apply(P.STOKES_OP_MG_A, ba)
     assert info["mg_levels_S"] == len(lv) - 1
     assert info["mg_levels_A"] == len(nsA) - 1
-    ref = cycle(lv, Ps, b, gs, SCALE_S)
+    nv = 2 if two_visits(lv, gs, visits) else 1
+    ref = cycle(lv, Ps, b, gs, SCALE_S, visits=nv)
     err = np.abs(z - ref).max() / np.abs(ref).max()
-    say(f"    N={N} gs={gs} SIMPLE V-cycle: levels {[x[0] for x in lv]} max rel err {err:.2e}")
+    say(f"    N={N} gs={gs} visits of level 1: {nv} SIMPLE cycle: levels {[x[0] for x in lv]} max rel err {err:.2e}")
     assert err < VC_TOL
     # A: block-diagonal over the three face planes, one hierarchy per plane
     if len(nsA) < 2:
@@ -183,3 +204,24 @@ def test_coarse_gauss_seidel_and_jacobi_agree(P, N, seed):
         f"gs: outer={b['outer_iters']} innerA={b['inner_A_iters']} innerS={b['inner_S_iters']}")
     assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
     assert abs(a["k_hat"] - b["k_hat"]) <= 1e-7 * abs(a["k_hat"])
+
+
+@pytest.mark.parametrize("mask_fn", [lambda: spheres(128, 3.0, 0.2, 0), lambda: spheres(128, 6.0, 0.5, 0)],
+                         ids=["tight", "spheres"])
+def test_two_visits_keep_the_outer_trajectory(P, mask_fn):
+    """One or two visits of level 1 change only the inner iteration counts: the
+    inner solves meet the same tolerance, so the outer count (+-1) and the
+    permeability (1e-8) stay; two visits need fewer inner SIMPLE iterations."""
+    m = mask_fn()
+    res = {}
+    with P.Stokes(m) as s:
+        for v in (1, 2):
+            s.set_option("mg_visits", v)
+            res[v] = s.solve(P.STOKES_SIMPLE, 1e-8)
+    a, b = res[1], res[2]
+    say(f"    one visit: outer={a['outer_iters']} innerS={a['inner_S_iters']}  "
+        f"two visits: outer={b['outer_iters']} innerS={b['inner_S_iters']}")
+    assert a["status"] == 0 and b["status"] == 0
+    assert abs(a["outer_iters"] - b["outer_iters"]) <= 1
+    assert abs(a["k_hat"] - b["k_hat"]) <= 1e-8 * abs(a["k_hat"])
+    assert b["inner_S_iters"] < a["inner_S_iters"]
