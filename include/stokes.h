@@ -276,12 +276,21 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *   "mg_visits"   visits of level 1 per cycle of the SIMPLE matrix.  Two
  *                 visits: after the first visit's result y_1, a second cycle
  *                 from level 1 down on the residual b_1 - A_1 y_1, its result
- *                 added to y_1 (the cycle stays linear and symmetric); only
- *                 where level 1 has a side of at least 64, is not the coarsest
- *                 and runs damped Jacobi ("mg_coarse_gs" not 2).  0 (default):
- *                 two visits where level 1 has a side of at least 128 (boxes
- *                 of 256 and more); 1: always one (the plain V-cycle); 2: two
- *                 wherever allowed.
+ *                 added to y_1 (the cycle stays linear and symmetric, and
+ *                 positive definite while the eigenvalues of B_1 A_1 stay below
+ *                 2, B_1 being the cycle from level 1 down); only where level 1
+ *                 has a side of at least 64, is not the coarsest and runs damped
+ *                 Jacobi ("mg_coarse_gs" not 2).  0 (default): two visits on
+ *                 plain contexts whose level 1 has a side of at least 128, if a
+ *                 power iteration at the first solve (20 products B_1 A_1 x)
+ *                 puts the largest eigenvalue below 1.8 -- when it does not and
+ *                 "mg_scale_deep" is unset, it retries with the corrections
+ *                 below level 1 scaled by 1.3 and keeps that scale if the
+ *                 estimate then passes; 1: always one visit (the plain
+ *                 V-cycle); 2: two wherever allowed, with no estimate.
+ *                 Report flag STOKES_FLAG_MG_TWO_VISITS tells which was used.
+ *   "mg_scale_deep" scale of the SIMPLE matrix's coarse corrections into
+ *                 levels 2 and below (default 0: "mg_scale")
  *   "precision"   0: FP64 throughout (default); 1: mixed -- inner solves with
  *                 A and with the SIMPLE matrix in FP32 (dot products accumulated
  *                 in FP64), outer flexible CG, true residual and permeability

@@ -98,7 +98,7 @@ def two_visits(levels, gs, visits):
     return allowed and (visits == 2 or (visits == 0 and levels[1][0] >= 128))
 
 
-def cycle(levels, Ps, b, gs, scale, l=0, visits=1):
+def cycle(levels, Ps, b, gs, scale, l=0, visits=1, deep=None):
     n, A, inv = levels[l]
     L = len(levels) - 1
     if l == L:
@@ -115,13 +115,14 @@ def cycle(levels, Ps, b, gs, scale, l=0, visits=1):
     else:
         x = OMEGA * inv * b
     bc = Ps[l].T @ (b - A @ x)
-    xc = cycle(levels, Ps, bc, gs, scale, l + 1)
+    xc = cycle(levels, Ps, bc, gs, scale, l + 1, deep=deep)
     if l == 0 and visits == 2:
         # second visit of level 1 on the residual the first leaves, added to its result
         _, Ac, invc = levels[1]
         w = np.where(invc > 0, bc - Ac @ xc, 0.0)
-        xc = xc + cycle(levels, Ps, w, gs, scale, 1)
-    x = x + scale * (Ps[l] @ xc)
+        xc = xc + cycle(levels, Ps, w, gs, scale, 1, deep=deep)
+    # corrections into levels 2 and below may take their own scale
+    x = x + (deep if (deep is not None and l >= 2) else scale) * (Ps[l] @ xc)
     if use_gs:
         x = relax(A, inv, x, b, blk)
         return relax(A, inv, x, b, ~blk)
@@ -135,12 +136,12 @@ def embed(M, pos, n3):
     return (E @ M @ E.T).tocsr()
 
 
-CASES = [(36, 2, 1, 0), (48, 5, 1, 0), (128, 0, 1, 0), (36, 2, 0, 2), (48, 5, 0, 2), (128, 0, 0, 2), (128, 0, 2, 2),
-         (128, 0, 1, 2)]
+CASES = [(36, 2, 1, 0, 0), (48, 5, 1, 0, 0), (128, 0, 1, 0, 0), (36, 2, 0, 2, 0), (48, 5, 0, 2, 0), (128, 0, 0, 2, 0),
+         (128, 0, 2, 2, 0), (128, 0, 1, 2, 0), (128, 0, 1, 2, 1.3)]
 
 
-@pytest.mark.parametrize("N,seed,gs,visits", CASES)
-def test_vcycle_matches_model(P, N, seed, gs, visits):
+@pytest.mark.parametrize("N,seed,gs,visits,deep", CASES)
+def test_vcycle_matches_model(P, N, seed, gs, visits, deep):
     m = spheres(N, 3.0 if N < 128 else 6.0, 0.45 if N < 128 else 0.5, seed)
     o = oracle.Oracle(m)
     n3 = N ** 3
@@ -159,6 +160,7 @@ def test_vcycle_matches_model(P, N, seed, gs, visits):
     with P.Stokes(m) as s:
         s.set_option("mg_coarse_gs", gs)
         s.set_option("mg_visits", visits)
+        s.set_option("mg_scale_deep", deep)
         info = s.info()
         z = s.apply(P.STOKES_OP_MG_SHAT, b).reshape(-1)
         if len(nsA) > 1:
@@ -170,7 +172,7 @@ def test_vcycle_matches_model(P, N, seed, gs, visits):
     assert info["mg_levels_S"] == len(lv) - 1
     assert info["mg_levels_A"] == len(nsA) - 1
     nv = 2 if two_visits(lv, gs, visits) else 1
-    ref = cycle(lv, Ps, b, gs, SCALE_S, visits=nv)
+    ref = cycle(lv, Ps, b, gs, SCALE_S, visits=nv, deep=deep or None)
     err = np.abs(z - ref).max() / np.abs(ref).max()
     say(f"    N={N} gs={gs} visits of level 1: {nv} SIMPLE cycle: levels {[x[0] for x in lv]} max rel err {err:.2e}")
     assert err < VC_TOL
