@@ -279,16 +279,10 @@ def host_cpu_model():
     return "unknown CPU"
 
 
-# The FP64 SIMPLE solve runs these sweeps in their software-pipelined forms
-# (the library's default, option mg_pipe); the timing kinds keep the plain names.
-PIPELINED_SYMBOLS = {"k_mgf_update_restrict<S>": "k_mgf_update_restrict_S_pipe<double>",
-                     "k_mgf_tiled<S,smooth>": "k_mgf_smooth_S_pipe<double>",
-                     "k_cgS_dirstencil_tiled": "k_cgS_dirstencil_pipe<double>"}
-
-
 def kernel_symbol(kind_name, precision):
-    if precision == "fp64" and kind_name in PIPELINED_SYMBOLS:
-        return PIPELINED_SYMBOLS[kind_name]
+    """The kernel symbol a timing kind names (the pipelined forms are FP64 only)."""
+    if kind_name.endswith("_pipe"):
+        return kind_name + "<double>"
     return kind_name
 
 

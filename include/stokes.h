@@ -395,7 +395,9 @@ stokes_status stokes_info(stokes_ctx *ctx, int64_t info[12]);
  * 8 = SIMPLE restriction, 9 = SIMPLE smoothing, 10 = A update fused with the
  * restriction, 11 = SIMPLE update fused with the restriction, 12 = A
  * direction fused with the stencil, 13 = SIMPLE direction fused with the
- * stencil (10..13: the multigrid-preconditioned solves).  Returns the total
+ * stencil (10..13: the multigrid-preconditioned solves), and the FP64 SIMPLE
+ * solve's software-pipelined forms ("mg_pipe"): 14 = update fused with the
+ * restriction, 15 = smoothing, 16 = direction fused with the stencil.  Returns the total
  * milliseconds and the number of timed launches (launches queued after
  * convergence return at once and are counted too), and the algorithmic bytes one launch
  * moves (each input read once, each output written once, in FP64). */

@@ -292,6 +292,22 @@ __global__ void k_inv_diag_Shat(Sweep s, const uint8_t* __restrict__ code, doubl
     }
 }
 
+// The states of a voxel's six faces in 16 bits: its code (lower faces, bits
+// 0-7) and, in the same encoding, its upper faces -- the x-state of the +x
+// neighbour's code, the y-state of the +y neighbour's and the z-state of the
+// +z neighbour's (bits 8-15).  Lets a sweep form the SIMPLE matrix's stencil
+// and diagonal at a voxel from one load.
+__global__ void k_code2(Sweep s, const uint8_t* __restrict__ code, uint16_t* __restrict__ code2) {
+    shift_nn((size_t)blockIdx.y * s.bstride, code, code2);
+    const Column c = sweep_column(s);
+    if (!c.valid) return;
+    for (int k = c.k0; k < c.k1; ++k) {
+        const Nbr n = neighbours(s, c, k);
+        const int up = sx_of(code[n.xp]) + 6 * sy_of(code[n.yp]) + 36 * sz_of(code[n.zp]);
+        code2[n.X] = (uint16_t)(code[n.X] | (up << 8));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Plain operators (no reductions)
 // ---------------------------------------------------------------------------
@@ -998,11 +1014,11 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_tiled(Sweep s, const 
 }
 
 // k_cgS_dirstencil_tiled with its loads software-pipelined over the z-march:
-// at plane k a thread issues the loads of its own column at k + 2 (code, z,
-// din) and of its ring point at k + 1, and forms the direction from the values
-// loaded one plane earlier, so the loads have a whole plane to arrive; the
-// codes of the +x and +y neighbours come from an LDS tile.  Same arithmetic as
-// the unpipelined kernel, point by point.
+// at plane k a thread issues the loads of its own column at k + 2 (16-bit
+// code, z, din) and of its ring point at k + 1 (z, din), and forms the
+// direction from the values loaded one plane earlier, so the loads have a
+// whole plane to arrive; the own 16-bit code (k_code2) gives the weights of
+// all six faces.  Same arithmetic as the unpipelined kernel, point by point.
 template <class T>
 struct CgsRaw {
     int cd;
@@ -1010,11 +1026,11 @@ struct CgsRaw {
 };
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const uint8_t* __restrict__ code,
+__global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const uint16_t* __restrict__ code2,
                                                                 const T* __restrict__ z, const T* __restrict__ din,
                                                                 T* __restrict__ dout, T* __restrict__ q, CgState* st,
                                                                 double* part) {
-    shift_nn((size_t)blockIdx.y * s.bstride, code, z, din, dout, q, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code2, z, din, dout, q, st, part);
     if (st->done) return;
     double beta_d;
     int j;
@@ -1022,7 +1038,6 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const u
     const T beta = (T)beta_d;
     const bool first = j == 0;
     __shared__ T tl[2][kTileMax];
-    __shared__ int ctl[2][kTileMax];
     __shared__ FaceTab<T> ft;
     face_tab_fill<T>(ft);
     const Tile t = tile_of(s);
@@ -1031,9 +1046,14 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const u
     const int col = t.wi + N * t.wj;
     const int hcol = t.hi + N * t.hj;
     // din is read also when the first iteration ignores it (an allocated
-    // vector), so no branch on the iteration sits between the loads
+    // vector), so no branch on the iteration sits between the loads.  The own
+    // column's 16-bit code gives all six face weights; ring points need none.
     auto load = [&](CgsRaw<T>& w, int X) {
-        w.cd = code[X];
+        w.cd = code2[X];
+        w.z = z[X];
+        w.di = din[X];
+    };
+    auto loadh = [&](CgsRaw<T>& w, int X) {
         w.z = z[X];
         w.di = din[X];
     };
@@ -1044,26 +1064,22 @@ __global__ void __launch_bounds__(kBlock) k_cgS_dirstencil_pipe(Sweep s, const u
     T dprev = dn(ra), dcur = dn(rb);
     int ccur = rb.cd;
     load(ra, col + tile_zw(t.k0 + 1, N) * N2);
-    if (ring) load(ha, hcol + t.k0 * N2);
+    if (ring) loadh(ha, hcol + t.k0 * N2);
     double acc[1] = {0.0};
     int buf = 0;
     auto plane = [&](int k, const CgsRaw<T>& rfin, CgsRaw<T>& rload, const CgsRaw<T>& hfin, CgsRaw<T>& hload) {
         load(rload, col + tile_zw(k + 2, N) * N2);
-        if (ring) load(hload, hcol + tile_zw(k + 1, N) * N2);
+        if (ring) loadh(hload, hcol + tile_zw(k + 1, N) * N2);
         const T dnext = dn(rfin);
         const int cnext = rfin.cd;
-        if (ring) {
-            tl[buf][hslot] = dn(hfin);
-            ctl[buf][hslot] = hfin.cd;
-        }
+        if (ring) tl[buf][hslot] = dn(hfin);
         tl[buf][own] = dcur;
-        ctl[buf][own] = ccur;
         __syncthreads();
         const T* w = tl[buf];
-        const int cxp = ctl[buf][own + 1], cyp = ctl[buf][own + W];
-        const T qv = ((ft.inv[0][ccur] * (dcur - w[own - 1]) + ft.inv[0][cxp] * (dcur - w[own + 1])) +
-                      (ft.inv[1][ccur] * (dcur - w[own - W]) + ft.inv[1][cyp] * (dcur - w[own + W]))) +
-                     (ft.inv[2][ccur] * (dcur - dprev) + ft.inv[2][cnext] * (dcur - dnext));
+        const int lo = ccur & 255, up = ccur >> 8;
+        const T qv = ((ft.inv[0][lo] * (dcur - w[own - 1]) + ft.inv[0][up] * (dcur - w[own + 1])) +
+                      (ft.inv[1][lo] * (dcur - w[own - W]) + ft.inv[1][up] * (dcur - w[own + W]))) +
+                     (ft.inv[2][lo] * (dcur - dprev) + ft.inv[2][up] * (dcur - dnext));
         if (t.valid) {
             dout[col + k * N2] = dcur;
             q[col + k * N2] = qv;

@@ -382,31 +382,38 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
 // thread issues the raw loads of its own column at k + 2 and of its ring point
 // at k + 1, and finishes the values loaded one plane earlier, so every load has
 // a whole plane (barrier and stencil) to arrive instead of being waited for in
-// the plane that issued it.  The codes of the +x and +y neighbours come from an
-// LDS tile filled beside the values.  Same arithmetic as the unpipelined
-// kernel, point by point.
+// the plane that issued it.  A point's six face states come from its 16-bit
+// code (k_code2), so it needs neither the stored 1/D nor its neighbours'
+// codes: 1/D is recomputed with the arithmetic of k_inv_diag_Shat (bitwise the
+// stored value).  Same arithmetic as the unpipelined kernel, point by point.
+template <class T>
+__device__ __forceinline__ T inv_dS_of(int c2, const FaceTab<T>& ft) {
+    const int lo = c2 & 255, up = c2 >> 8;
+    const T dS = ((ft.inv[0][lo] + ft.inv[0][up]) + (ft.inv[1][lo] + ft.inv[1][up])) + (ft.inv[2][lo] + ft.inv[2][up]);
+    return dS > T(0) ? T(1) / dS : T(0);
+}
+
+// the SIMPLE matrix at level 0 from a point's 16-bit code (lower and upper faces)
+template <class T>
+__device__ __forceinline__ T mgf_apply_S2(const T (&v)[7], int c2, const FaceTab<T>& ft) {
+    const int lo = c2 & 255, up = c2 >> 8;
+    return mgf_apply<T, kMgFineShat>(v, lo, up, up, up, 0, ft);
+}
+
 template <class T>
 struct MgfRawS {
     int cd;
-    T inv, b, e;
+    T b, e;
 };
 
 template <class T>
 __device__ __forceinline__ void mgfs_load(MgfRawS<T>& q, int N, int cn, int i, int j, int k,
-                                          const uint8_t* __restrict__ code, const T* __restrict__ invd,
-                                          const T* __restrict__ b, const T* __restrict__ xc) {
+                                          const uint16_t* __restrict__ code2, const T* __restrict__ b,
+                                          const T* __restrict__ xc) {
     const int X = i + N * (j + N * k);
-    q.cd = code[X];
-    q.inv = invd[X];
+    q.cd = code2[X];
     q.b = b[X];
     q.e = xc[(i >> 1) + cn * ((j >> 1) + cn * (k >> 1))];
-}
-
-template <class T>
-__device__ __forceinline__ T mgfs_x(const MgfRawS<T>& q, T scale, T omega) {
-    T x = omega * q.inv * q.b;
-    if (q.inv > T(0)) x += scale * q.e;
-    return x;
 }
 
 template <class T>
@@ -416,15 +423,13 @@ struct MgfPtS {
 };
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, const uint8_t* __restrict__ code,
-                                                              const T* __restrict__ invd, const T* __restrict__ b,
-                                                              const T* __restrict__ xc, T scale, T omega,
-                                                              T* __restrict__ out, double* part, int slot,
-                                                              const CgState* st) {
-    shift_nn((size_t)blockIdx.y * s.bstride, code, invd, b, xc, out, part);
+__global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, const uint16_t* __restrict__ code2,
+                                                              const T* __restrict__ b, const T* __restrict__ xc,
+                                                              T scale, T omega, T* __restrict__ out, double* part,
+                                                              int slot, const CgState* st) {
+    shift_nn((size_t)blockIdx.y * s.bstride, code2, b, xc, out, part);
     shift_all((size_t)blockIdx.y * s.bstride, st);
     __shared__ T tile[2][kTileMax];
-    __shared__ int ctile[2][kTileMax];
     __shared__ FaceTab<T> ft;
     face_tab_fill<T>(ft);
     __syncthreads();
@@ -433,23 +438,25 @@ __global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, c
     const int wi = tt.wi, wj = tt.wj, k0 = tt.k0, k1 = tt.k1;
     const int hi = tt.hi, hj = tt.hj, hslot = tt.hslot, own = tt.own;
     auto zw = [N](int k) { return k < 0 ? k + N : (k >= N ? k - N : k); };
-    auto finish = [scale, omega](const MgfRawS<T>& q) {
+    const FaceTab<T>& ftr = ft;
+    auto finish = [scale, omega, &ftr](const MgfRawS<T>& q) {
         MgfPtS<T> p;
         p.cd = q.cd;
-        p.inv = q.inv;
+        p.inv = inv_dS_of<T>(q.cd, ftr);
         p.b = q.b;
-        p.x = mgfs_x<T>(q, scale, omega);
+        p.x = omega * p.inv * q.b;
+        if (p.inv > T(0)) p.x += scale * q.e;
         return p;
     };
 
     // two sets of raw loads alternate between the planes of an unrolled pair,
     // so no register that a load is still filling is copied at the loop's end
     MgfRawS<T> ra, rb, ha, hb;
-    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 - 1), code, invd, b, xc);
-    mgfs_load<T>(rb, N, cn, wi, wj, k0, code, invd, b, xc);
-    const T x_first = mgfs_x<T>(ra, scale, omega);
-    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 + 1), code, invd, b, xc);
-    if (tt.ring) mgfs_load<T>(ha, N, cn, hi, hj, k0, code, invd, b, xc);
+    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 - 1), code2, b, xc);
+    mgfs_load<T>(rb, N, cn, wi, wj, k0, code2, b, xc);
+    const T x_first = finish(ra).x;
+    mgfs_load<T>(ra, N, cn, wi, wj, zw(k0 + 1), code2, b, xc);
+    if (tt.ring) mgfs_load<T>(ha, N, cn, hi, hj, k0, code2, b, xc);
     // a finished solve is checked after the first loads (in bounds either way)
     if (st && st->done) return;
     T xprev = x_first;
@@ -459,19 +466,15 @@ __global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, c
     // plane k: issue the loads of k + 2 (own) and k + 1 (ring), finish k + 1
     // (own) and k (ring) from the loads issued one plane earlier
     auto plane = [&](int k, const MgfRawS<T>& rfin, MgfRawS<T>& rload, const MgfRawS<T>& hfin, MgfRawS<T>& hload) {
-        mgfs_load<T>(rload, N, cn, wi, wj, zw(k + 2), code, invd, b, xc);
-        if (tt.ring) mgfs_load<T>(hload, N, cn, hi, hj, zw(k + 1), code, invd, b, xc);
+        mgfs_load<T>(rload, N, cn, wi, wj, zw(k + 2), code2, b, xc);
+        if (tt.ring) mgfs_load<T>(hload, N, cn, hi, hj, zw(k + 1), code2, b, xc);
         const MgfPtS<T> nxt = finish(rfin);
-        if (tt.ring) {
-            tile[buf][hslot] = mgfs_x<T>(hfin, scale, omega);
-            ctile[buf][hslot] = hfin.cd;
-        }
+        if (tt.ring) tile[buf][hslot] = finish(hfin).x;
         tile[buf][own] = cur.x;
-        ctile[buf][own] = cur.cd;
         __syncthreads();
         const T* tl = tile[buf];
         const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
-        const T ax = mgf_apply<T, kMgFineShat>(v, cur.cd, ctile[buf][own + 1], ctile[buf][own + W], nxt.cd, 0, ft);
+        const T ax = mgf_apply_S2<T>(v, cur.cd, ft);
         const T yv = cur.inv > T(0) ? v[0] + omega * cur.inv * (cur.b - ax) : T(0);
         if (tt.valid) {
             out[wi + N * (wj + N * k)] = yv;
@@ -662,39 +665,35 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict(Sweep s, const u
 template <class T>
 struct MgfRawU {
     int cd;
-    T inv, r, q;
+    T r, q;
 };
 
 template <class T>
-__device__ __forceinline__ void mgfu_load(MgfRawU<T>& w, int X, const uint8_t* __restrict__ code,
-                                          const T* __restrict__ invd, const T* __restrict__ r,
-                                          const T* __restrict__ q) {
-    w.cd = code[X];
-    w.inv = invd[X];
+__device__ __forceinline__ void mgfu_load(MgfRawU<T>& w, int X, const uint16_t* __restrict__ code2,
+                                          const T* __restrict__ r, const T* __restrict__ q) {
+    w.cd = code2[X];
     w.r = r[X];
     w.q = q[X];
 }
 
 template <class T>
-__device__ __forceinline__ MgfPtS<T> mgfu_finish(const MgfRawU<T>& w, T alpha, T omega) {
+__device__ __forceinline__ MgfPtS<T> mgfu_finish(const MgfRawU<T>& w, T alpha, T omega, const FaceTab<T>& ft) {
     MgfPtS<T> p;
     p.cd = w.cd;
-    p.inv = w.inv;
+    p.inv = inv_dS_of<T>(w.cd, ft);
     p.b = w.r - alpha * w.q;
     p.x = omega * p.inv * p.b;
     return p;
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, const uint8_t* __restrict__ code,
-                                                                       const T* __restrict__ invd, T* __restrict__ x,
-                                                                       const T* __restrict__ r, T* __restrict__ rout,
-                                                                       const T* __restrict__ d,
+__global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, const uint16_t* __restrict__ code2,
+                                                                       T* __restrict__ x, const T* __restrict__ r,
+                                                                       T* __restrict__ rout, const T* __restrict__ d,
                                                                        const T* __restrict__ q, T* __restrict__ bc,
                                                                        T omega, CgState* st, double* part) {
-    shift_nn((size_t)blockIdx.y * s.bstride, code, invd, x, r, rout, d, q, bc, st, part);
+    shift_nn((size_t)blockIdx.y * s.bstride, code2, x, r, rout, d, q, bc, st, part);
     __shared__ T tile[2][kTileMax];
-    __shared__ int ctile[2][kTileMax];
     __shared__ T pair_lds[kBlock / 2];
     __shared__ FaceTab<T> ft;
     const Tile tt = tile_of(s);
@@ -708,33 +707,29 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, 
     // the first planes' loads go out before alpha is reduced (in bounds
     // whether or not the solve has finished)
     MgfRawU<T> ra, rb, ha, hb;
-    mgfu_load<T>(ra, col + zw(k0 - 1) * N2, code, invd, r, q);
-    mgfu_load<T>(rb, col + k0 * N2, code, invd, r, q);
+    mgfu_load<T>(ra, col + zw(k0 - 1) * N2, code2, r, q);
+    mgfu_load<T>(rb, col + k0 * N2, code2, r, q);
     if (st->done) return;
     double alpha_d;
     if (cg_update_scalars(st, part, s.nblk, &alpha_d)) return;
     const T alpha = (T)alpha_d;
     face_tab_fill<T>(ft);
     __syncthreads();
-    T xprev = mgfu_finish<T>(ra, alpha, omega).x;
-    MgfPtS<T> cur = mgfu_finish<T>(rb, alpha, omega);
-    mgfu_load<T>(ra, col + zw(k0 + 1) * N2, code, invd, r, q);
-    if (ring) mgfu_load<T>(ha, hcol + k0 * N2, code, invd, r, q);
+    T xprev = mgfu_finish<T>(ra, alpha, omega, ft).x;
+    MgfPtS<T> cur = mgfu_finish<T>(rb, alpha, omega, ft);
+    mgfu_load<T>(ra, col + zw(k0 + 1) * N2, code2, r, q);
+    if (ring) mgfu_load<T>(ha, hcol + k0 * N2, code2, r, q);
     double acc[2] = {0.0, 0.0};
     T rsum = T(0);
     int buf = 0;
     // plane k: issue the loads of k + 2 (own) and k + 1 (ring), finish k + 1
     // (own) and k (ring) from the loads issued one plane earlier
     auto plane = [&](int k, const MgfRawU<T>& rfin, MgfRawU<T>& rload, const MgfRawU<T>& hfin, MgfRawU<T>& hload) {
-        mgfu_load<T>(rload, col + zw(k + 2) * N2, code, invd, r, q);
-        if (ring) mgfu_load<T>(hload, hcol + zw(k + 1) * N2, code, invd, r, q);
-        const MgfPtS<T> nxt = mgfu_finish<T>(rfin, alpha, omega);
-        if (ring) {
-            tile[buf][hslot] = mgfu_finish<T>(hfin, alpha, omega).x;
-            ctile[buf][hslot] = hfin.cd;
-        }
+        mgfu_load<T>(rload, col + zw(k + 2) * N2, code2, r, q);
+        if (ring) mgfu_load<T>(hload, hcol + zw(k + 1) * N2, code2, r, q);
+        const MgfPtS<T> nxt = mgfu_finish<T>(rfin, alpha, omega, ft);
+        if (ring) tile[buf][hslot] = mgfu_finish<T>(hfin, alpha, omega, ft).x;
         tile[buf][own] = cur.x;
-        ctile[buf][own] = cur.cd;
         // own point: the CG update proper
         if (valid) {
             const int X = col + k * N2;
@@ -747,7 +742,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, 
         __syncthreads();
         const T* tl = tile[buf];
         const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
-        rsum += cur.b - mgf_apply<T, kMgFineShat>(v, cur.cd, ctile[buf][own + 1], ctile[buf][own + W], nxt.cd, 0, ft);
+        rsum += cur.b - mgf_apply_S2<T>(v, cur.cd, ft);
         if (k & 1) {
             const int cN = N >> 1;
             T rs[1] = {rsum};

@@ -50,7 +50,7 @@ constexpr int kCompBlocks = 256;
 enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeSStencil = 4, kTimeSUpdate = 5,
        kTimeMgARestrict = 6, kTimeMgASmooth = 7, kTimeMgSRestrict = 8, kTimeMgSSmooth = 9,
        kTimeAUpdRestrict = 10, kTimeSUpdRestrict = 11, kTimeADirStencil = 12, kTimeSDirStencil = 13,
-       kTimeKinds = 14 };
+       kTimeSUpdRestrictPipe = 14, kTimeMgSSmoothPipe = 15, kTimeSDirStencilPipe = 16, kTimeKinds = 17 };
 // A dir     : r, d read (3 planes each), code byte read; d written
 // A stencil : d read, code byte read; q written
 // A update  : x, d, r, q read, code byte read; x, r written
@@ -66,10 +66,15 @@ enum { kTimeADir = 0, kTimeAStencil = 1, kTimeAUpdate = 2, kTimeSDir = 3, kTimeS
 // S update + restriction: inverse diagonal, x, r, d, q read, code byte; x, r written, level-1 b written
 // A direction + stencil: z, d read (3 planes), code byte; d, q written (3 planes)
 // S direction + stencil: z, d read, code byte; d, q written
+// the FP64 SIMPLE solve's software-pipelined forms (option mg_pipe):
+// S update + restriction: x, r, d, q read, 16-bit code; x, r written, level-1 b written
+// S smoothing: b, 16-bit code, level-1 x read; y written
+// S direction + stencil: z, d read, 16-bit code; d, q written
 constexpr double kBytesPerCell[kTimeKinds] = {9 * 8 + 1,     6 * 8 + 1,         18 * 8 + 1,    4 * 8,
                                               2 * 8 + 1,     7 * 8,             3 * 8 + 1 + 3, 6 * 8 + 1 + 3,
                                               2 * 8 + 1 + 1, 3 * 8 + 1 + 1,     18 * 8 + 1 + 3, 7 * 8 + 1 + 1,
-                                              12 * 8 + 1,    4 * 8 + 1};
+                                              12 * 8 + 1,    4 * 8 + 1,         6 * 8 + 2 + 1, 2 * 8 + 2 + 1,
+                                              4 * 8 + 2};
 
 }  // namespace
 
@@ -123,6 +128,7 @@ struct stokes_ctx {
     double* fd = nullptr;                                               // faces, inner direction
     double *p = nullptr, *r = nullptr, *zs = nullptr, *d = nullptr, *q = nullptr;  // cells
     double *sr = nullptr, *sq = nullptr, *invdS = nullptr;                         // cells (SIMPLE solve)
+    uint16_t* code2 = nullptr;     // lower and upper face states of every voxel (k_code2)
     double* sd = nullptr;                                                          // cells, inner direction
     // FP32 inner-solve vectors of the mixed-precision path (allocated on first use)
     float *fx32 = nullptr, *fr32 = nullptr, *fd32 = nullptr, *fq32 = nullptr;     // faces
@@ -831,13 +837,15 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
     }
     const T* xc1 = h.levels == 1 ? mg_view(h, 1, T()).x : mg_view(h, 1, T()).y;
     bool open;
-    ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : kTimeMgSSmooth, &open));
+    const bool pipe = !kindA && c->mg_pipe && sizeof(T) == 8;
+    ST_TRY(time_begin(c, kindA ? kTimeMgASmooth : (pipe ? kTimeMgSSmoothPipe : kTimeMgSSmooth), &open));
     if (kindA)
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineA, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
-    else if (c->mg_pipe && sizeof(T) == 8)
+    else if (pipe)
+        // (1/D from the 16-bit codes: the same values as invd0, which is c->invdS here)
         hipLaunchKernelGGL(k_mgf_smooth_S_pipe<T>, grid_of(s0), dim3(kBlock), 0, c->stream, s0, h.grid[1].n,
-                           c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
+                           c->code2, b0, xc1, scale, omega, z0, c->part, kRZ, st);
     else
         hipLaunchKernelGGL((k_mgf_tiled<T, kMgFineShat, true>), grid_of(s0), dim3(kBlock), 0, c->stream, s0,
                            h.grid[1].n, c->code, invd0, b0, xc1, scale, omega, z0, c->part, kRZ, st);
@@ -963,9 +971,9 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
         T* dout = parity ? v.d : d2;
         bool open;
         if (fuse) {
-            ST_TRY(time_begin(c, kTimeSDirStencil, &open));
+            ST_TRY(time_begin(c, pipe ? kTimeSDirStencilPipe : kTimeSDirStencil, &open));
             if (pipe)
-                hipLaunchKernelGGL(k_cgS_dirstencil_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
+                hipLaunchKernelGGL(k_cgS_dirstencil_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code2,
                                    (const T*)z, (const T*)din, dout, v.q, st, c->part);
             else
                 hipLaunchKernelGGL(k_cgS_dirstencil_tiled<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
@@ -983,11 +991,10 @@ stokes_status cg_S_mg(stokes_ctx* c, InnerS<T> v, const double* b, double eps, i
                                v.q, st, c->part);
             ST_TRY(time_end(c, open));
         }
-        ST_TRY(time_begin(c, kTimeSUpdRestrict, &open));
+        ST_TRY(time_begin(c, pipe ? kTimeSUpdRestrictPipe : kTimeSUpdRestrict, &open));
         if (pipe)
-            hipLaunchKernelGGL(k_mgf_update_restrict_S_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code,
-                               (const T*)v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega,
-                               st, c->part);
+            hipLaunchKernelGGL(k_mgf_update_restrict_S_pipe<T>, grid_of(s), dim3(kBlock), 0, c->stream, s, c->code2,
+                               v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega, st, c->part);
         else
             hipLaunchKernelGGL((k_mgf_update_restrict<T, kMgFineShat>), grid_of(s), dim3(kBlock), 0, c->stream, s,
                                c->code, v.invd, v.x, (const T*)rin, rout, (const T*)dout, (const T*)v.q, bc, omega,
@@ -1287,6 +1294,7 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* const* masks) {
     const int K = std::max(1, c->ncomp_kept);
     ST_TRY(dev_alloc(c, &c->bits, (size_t)N * N * c->wpr));
     ST_TRY(dev_alloc(c, &c->code, (size_t)n3));
+    ST_TRY(dev_alloc(c, &c->code2, (size_t)n3));
     ST_TRY(dev_alloc(c, &c->comp_count, (size_t)K));
     ST_TRY(dev_alloc(c, &c->comp_part, (size_t)kCompBlocks * K));
     ST_TRY(dev_alloc(c, &c->proj_part, (size_t)kMaxBlocks));
@@ -1327,6 +1335,7 @@ static stokes_status setup_impl(stokes_ctx* c, const uint8_t* const* masks) {
     }
     hipLaunchKernelGGL(k_face_codes, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->bits, c->wpr, c->code);
     hipLaunchKernelGGL(k_inv_diag_Shat, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->invdS);
+    hipLaunchKernelGGL(k_code2, grid_of(c->sw), dim3(kBlock), 0, c->stream, c->sw, c->code, c->code2);
     HIP_TRY(hipGetLastError());
     ST_TRY(build_mg(c, c->mgS, 1, kMgFineShat));
     ST_TRY(build_mg(c, c->mgA, 3, kMgFineA));
@@ -1485,7 +1494,7 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
     const int64_t n3 = (int64_t)N * N * N, wpr = (N + 31) / 32;
     auto blk = [](int64_t count, int64_t size) { return std::max<int64_t>(count, 1) * size; };
     const int64_t K = kMaxCompLds;
-    int64_t t = blk((int64_t)N * N * wpr, 4) + blk(n3, 1) + blk(K, 8) + blk((int64_t)kCompBlocks * K, 8) +
+    int64_t t = blk((int64_t)N * N * wpr, 4) + blk(n3, 1) + blk(n3, 2) + blk(K, 8) + blk((int64_t)kCompBlocks * K, 8) +
                 blk(K, 8) + blk(n3, 2);
     t += 5 * blk(3 * n3, 8) + 9 * blk(n3, 8);
     t += blk(2, sizeof(CgState)) + blk((int64_t)kNumSlots * kMaxBlocks, 8) + blk(3 * (int64_t)kMaxBlocks, 8) +

@@ -328,7 +328,8 @@ def stokes_info(ctx):
 KERNEL_NAMES = ["k_cgA_dir", "k_cgA_stencil_tiled", "k_cgA_update", "k_cgS_dir", "k_cgS_stencil_tiled", "k_cgS_update",
                 "k_mgf_tiled<A,restrict>", "k_mgf_tiled<A,smooth>", "k_mgf_tiled<S,restrict>",
                 "k_mgf_tiled<S,smooth>", "k_mgf_update_restrict<A>", "k_mgf_update_restrict<S>",
-                "k_cgA_dirstencil_tiled", "k_cgS_dirstencil_tiled"]
+                "k_cgA_dirstencil_tiled", "k_cgS_dirstencil_tiled",
+                "k_mgf_update_restrict_S_pipe", "k_mgf_smooth_S_pipe", "k_cgS_dirstencil_pipe"]
 
 
 def stokes_kernel_timing(ctx, kernel):

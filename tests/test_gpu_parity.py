@@ -423,22 +423,26 @@ def test_multigrid_and_jacobi_inner_solves_agree(P, N, seed):
 def test_kernel_timing_counts_every_kind(P):
     """Sampled HIP-event timing covers every kernel the inner solves launch:
     with multigrid the direction, stencil, fused update + restriction and
-    level-0 smoothing kernels; with Jacobi the direction, stencil and update
-    kernels.  Bytes per launch follow the per-voxel byte model."""
+    level-0 smoothing kernels (the SIMPLE matrix's in their pipelined FP64 forms
+    by default, the plain forms with mg_pipe=0); with Jacobi the direction,
+    stencil and update kernels.  Bytes per launch follow the per-voxel byte
+    model."""
     from paper_2307_05266_amd.stokes import KERNEL_NAMES
     N = 32
-    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26, 148, 58, 97, 33]
+    per_voxel = [73, 49, 145, 32, 17, 56, 28, 52, 18, 26, 148, 58, 97, 33, 51, 19, 34]
     assert len(KERNEL_NAMES) == len(per_voxel)
     with P.Stokes(spheres(N, 3.0, 0.5, 1)) as s:
-        for mg, launched in [(1, {7, 9, 10, 11, 12, 13}), (0, {0, 1, 2, 3, 4, 5})]:
+        for mg, pipe, launched in [(1, 1, {7, 10, 12, 14, 15, 16}), (1, 0, {7, 9, 10, 11, 12, 13}),
+                                   (0, 1, {0, 1, 2, 3, 4, 5})]:
             s.set_option("mg", mg)
             s.set_option("mg_A", mg)
+            s.set_option("mg_pipe", pipe)
             s.set_option("fuse_dir_A", 1)
             s.set_option("kernel_timing", 1)
             s.solve(P.STOKES_SIMPLE, 1e-8)
             for kind, name in enumerate(KERNEL_NAMES):
                 ms, n, nbytes = s.kernel_timing(kind)
-                say(f"    mg={mg} {name}: {n} launches {ms:.3f} ms")
+                say(f"    mg={mg} pipe={pipe} {name}: {n} launches {ms:.3f} ms")
                 assert (n > 0 and ms > 0.0) == (kind in launched), name
                 assert nbytes == per_voxel[kind] * N ** 3
                 assert s.kernel_timing(kind)[1] == 0   # reset by the read
@@ -468,7 +472,8 @@ def test_graph_replay_matches_eager_launches(P, precision):
         s.set_option("kernel_timing", 3)
         r = s.solve(P.STOKES_SIMPLE, 1e-8)
         assert r["k_hat"] == ref["k_hat"]
-        assert s.kernel_timing(13)[1] > 0        # the SIMPLE direction + stencil kernel was timed
+        # the SIMPLE direction + stencil kernel was timed (pipelined form in FP64)
+        assert s.kernel_timing(16 if precision == 0 else 13)[1] > 0
 
 
 def test_fused_direction_matches_separate_kernels(P):
