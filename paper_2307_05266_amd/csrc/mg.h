@@ -131,7 +131,10 @@ struct MgOp {
     const uint8_t* code;
     int kind;           // level 0: kMgFineShat or kMgFineA
     const void* invd;   // level 0, SIMPLE matrix: inverse diagonal (T)
-    const void* D;      // levels >= 1
+    // levels >= 1: the Galerkin operator's diagonal and couplings, stored in
+    // FP32 for both precisions (the cycle is a preconditioner; its vectors and
+    // arithmetic keep the precision of the solve)
+    const void* D;
     const void* Wx;
     const void* Wy;
     const void* Wz;
@@ -779,10 +782,10 @@ template <class T>
 __device__ __forceinline__ void mgc_load(MgcPoint<T>& m, const MgGrid& g, const MgOp& op, const T* __restrict__ b,
                                          int p, int i, int j, int k) {
     const size_t o = (size_t)p * g.n3;
-    const T* D = (const T*)op.D + o;
-    const T* Wx = (const T*)op.Wx + o;
-    const T* Wy = (const T*)op.Wy + o;
-    const T* Wz = (const T*)op.Wz + o;
+    const float* D = (const float*)op.D + o;
+    const float* Wx = (const float*)op.Wx + o;
+    const float* Wy = (const float*)op.Wy + o;
+    const float* Wz = (const float*)op.Wz + o;
     const T* bp = b + o;
     const int idx[7] = {mg_idx(g, i, j, k),     mg_idx(g, i - 1, j, k), mg_idx(g, i + 1, j, k), mg_idx(g, i, j - 1, k),
                         mg_idx(g, i, j + 1, k), mg_idx(g, i, j, k - 1), mg_idx(g, i, j, k + 1)};
@@ -919,10 +922,10 @@ __device__ __forceinline__ void gs_row(GsRow<T>& r, const MgGrid& g, const MgOp&
     const size_t o = (size_t)k.p * g.n3;
     const int i = wrapc(k.o[0] + wx - 2, g.n), j = wrapc(k.o[1] + wy - 2, g.n), kk = wrapc(k.o[2] + wz - 2, g.n);
     const int X = i + g.n * (j + g.n * kk);
-    const T* D = (const T*)op.D + o;
-    const T* Wx = (const T*)op.Wx + o;
-    const T* Wy = (const T*)op.Wy + o;
-    const T* Wz = (const T*)op.Wz + o;
+    const float* D = (const float*)op.D + o;
+    const float* Wx = (const float*)op.Wx + o;
+    const float* Wy = (const float*)op.Wy + o;
+    const float* Wz = (const float*)op.Wz + o;
     r.b = b[o + X];
     r.d = D[X];
     r.w[0] = Wx[X];
@@ -973,7 +976,7 @@ template <class T, bool POST>
 __device__ __forceinline__ void gs_window_loads(const MgGrid& g, const GsBrick& k, const MgOp& op,
                                                 const T* __restrict__ b, const T* __restrict__ xc, int cn,
                                                 T (&bv)[kGsPer], T (&dv)[kGsPer], T* ev) {
-    const T* D = (const T*)op.D + (size_t)k.p * g.n3;
+    const float* D = (const float*)op.D + (size_t)k.p * g.n3;
     const T* bp = b + (size_t)k.p * g.n3;
     const T* xa = POST ? xc + (size_t)k.p * cn * cn * cn : nullptr;
 #pragma unroll
@@ -1113,8 +1116,8 @@ __device__ __forceinline__ void mgc_point(MgcPt<T, NB>& q, int n, int cn, int i,
     constexpr bool POST = MODE == kMgcPost || MODE == kMgcPostAcc;
     const size_t n3 = (size_t)n * n * n;
     const int X = i + n * (j + n * k);
-    const T* D = (const T*)op.D;
-    const T* Wz = (const T*)op.Wz;
+    const float* D = (const float*)op.D;
+    const float* Wz = (const float*)op.Wz;
     T e[NB];
     if (POST) {
         const size_t cn3 = (size_t)cn * cn * cn;
@@ -1157,8 +1160,8 @@ __global__ void __launch_bounds__(kBlock) k_mgc_tiled(Sweep s, int cn, MgOp op, 
     const Tile t = tile_of(s);
     const int n = t.N, W = t.W;
     const size_t n3 = (size_t)s.n3;
-    const T* Wx = (const T*)op.Wx;
-    const T* Wy = (const T*)op.Wy;
+    const float* Wx = (const float*)op.Wx;
+    const float* Wy = (const float*)op.Wy;
     auto zw = [n](int k) { return k < 0 ? k + n : (k >= n ? k - n : k); };
     MgcPt<T, NB> cur, nxt;
     T xprev[NB];
@@ -1265,10 +1268,10 @@ __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __r
         nbr[q][4] = base + mg_idx(g, i, j, k - 1);
         nbr[q][5] = base + mg_idx(g, i, j, k + 1);
         // the coarsest level is always an assembled (coarse) level
-        const T* D = (const T*)op.D;
-        const T* Wx = (const T*)op.Wx;
-        const T* Wy = (const T*)op.Wy;
-        const T* Wz = (const T*)op.Wz;
+        const float* D = (const float*)op.D;
+        const float* Wx = (const float*)op.Wx;
+        const float* Wy = (const float*)op.Wy;
+        const float* Wz = (const float*)op.Wz;
         dg[q] = D[Ic];
         w[q][0] = Wx[Ic];
         w[q][1] = Wx[nbr[q][1]];

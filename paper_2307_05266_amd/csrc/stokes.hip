@@ -144,7 +144,10 @@ struct stokes_ctx {
         struct Lev64 { double *D, *Wx, *Wy, *Wz, *b, *x, *y, *w; };
         struct Lev32 { float *D, *Wx, *Wy, *Wz, *b, *x, *y, *w; };
         std::vector<Lev64> l64;        // [1..levels]
-        std::vector<Lev32> l32;
+        std::vector<Lev32> l32;        // FP32 vectors; D, Wx, Wy, Wz point into c32
+        // the coarse operators in FP32, read by the cycle in both precisions
+        struct LevC { float *D, *Wx, *Wy, *Wz; };
+        std::vector<LevC> c32;         // [1..levels]
         double* z = nullptr;           // fine level: output of the cycle
         float* z32 = nullptr;
         double* r2 = nullptr;          // fine level: second residual buffer of the fused update
@@ -641,6 +644,19 @@ stokes_status build_mg(stokes_ctx* c, MgHier& h, int nb, int kind) {
         hipLaunchKernelGGL(k_mg_coarsen<double>, dim3((m + kBlock - 1) / kBlock, c->nbatch), dim3(kBlock), 0, c->stream,
                            h.grid[l], h.grid[l + 1], f.D, f.Wx, f.Wy, f.Wz, t.D, t.Wx, t.Wy, t.Wz);
     }
+    // the FP32 copies the cycle reads (each level's Galerkin product formed in FP64 first)
+    h.c32.assign(L + 1, {});
+    for (int l = 1; l <= L; ++l) {
+        auto& cc = h.c32[l];
+        const int m = nb * h.grid[l].n3;
+        for (float** a : {&cc.D, &cc.Wx, &cc.Wy, &cc.Wz}) ST_TRY(dev_alloc(c, a, (size_t)m));
+        const auto& d = h.l64[l];
+        const double* src[4] = {d.D, d.Wx, d.Wy, d.Wz};
+        float* dst[4] = {cc.D, cc.Wx, cc.Wy, cc.Wz};
+        for (int q = 0; q < 4; ++q)
+            hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m), c->nbatch), dim3(kBlock), 0, c->stream, m, src[q],
+                               dst[q], c->bstride);
+    }
     HIP_TRY(hipGetLastError());
     h.levels = L;
     return STOKES_OK;
@@ -654,14 +670,12 @@ stokes_status build_mg32(stokes_ctx* c, MgHier& h) {
     for (int l = 1; l <= L; ++l) {
         auto& lv = h.l32[l];
         const int m = h.nb * h.grid[l].n3;
-        for (float** a : {&lv.D, &lv.Wx, &lv.Wy, &lv.Wz, &lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, (size_t)m));
+        for (float** a : {&lv.b, &lv.x, &lv.y}) ST_TRY(dev_alloc(c, a, (size_t)m));
         if (l == 1) ST_TRY(dev_alloc(c, &lv.w, (size_t)m));
-        const auto& d = h.l64[l];
-        const double* src[4] = {d.D, d.Wx, d.Wy, d.Wz};
-        float* dst[4] = {lv.D, lv.Wx, lv.Wy, lv.Wz};
-        for (int q = 0; q < 4; ++q)
-            hipLaunchKernelGGL(k_narrow_flat, dim3(flat_blocks(m), c->nbatch), dim3(kBlock), 0, c->stream, m, src[q],
-                               dst[q], c->bstride);
+        lv.D = h.c32[l].D;
+        lv.Wx = h.c32[l].Wx;
+        lv.Wy = h.c32[l].Wy;
+        lv.Wz = h.c32[l].Wz;
     }
     ST_TRY(dev_alloc(c, &h.z32, (size_t)h.nb * c->n3));
     ST_TRY(dev_alloc(c, &h.r2_32, (size_t)h.nb * c->n3));
@@ -723,8 +737,8 @@ stokes_status mg_coarse(stokes_ctx* c, MgHier& h, int from, const T* bfrom, bool
     const T scale_deep = h.kind == kMgFineA ? scale0 : (T)mg_deep_scale(c);
     std::vector<MgOp> ops(L + 1);
     for (int l = 1; l <= L; ++l) {
-        auto v = mg_view(h, l, T());
-        ops[l] = {nullptr, 0, nullptr, v.D, v.Wx, v.Wy, v.Wz};
+        const auto& cc = h.c32[l];
+        ops[l] = {nullptr, 0, nullptr, cc.D, cc.Wx, cc.Wy, cc.Wz};
     }
     auto nodes = [&](int l) { return h.nb * h.grid[l].n3; };
     const bool kindA = h.kind == kMgFineA;
@@ -796,8 +810,8 @@ stokes_status mg_coarse(stokes_ctx* c, MgHier& h, int from, const T* bfrom, bool
 // w_1 = b_1 - A_1 y_1 on level 1 of a hierarchy (tiled level 1)
 template <class T>
 void mg_level1_residual(stokes_ctx* c, MgHier& h, const T* b1, const T* y1, T* w1, const CgState* st) {
-    auto v1 = mg_view(h, 1, T());
-    const MgOp op1 = {nullptr, 0, nullptr, v1.D, v1.Wx, v1.Wy, v1.Wz};
+    const auto& cc = h.c32[1];
+    const MgOp op1 = {nullptr, 0, nullptr, cc.D, cc.Wx, cc.Wy, cc.Wz};
     const Sweep& ls = h.sweep[1];
     hipLaunchKernelGGL((k_mgc_tiled<T, 1, kMgcResid>), grid_of(ls), dim3(kBlock), 0, c->stream, ls, h.grid[2].n, op1,
                        b1, y1, T(0), (T)c->mg_omega, w1, st);
@@ -1504,7 +1518,12 @@ stokes_status stokes_estimate_bytes(int N, unsigned flags, int precision, int64_
         if (ns.size() < 2) continue;
         for (int prec = 0; prec <= precision; ++prec) {
             const int64_t w = prec == 0 ? 8 : 4;
-            for (size_t l = 1; l < ns.size(); ++l) t += (l == 1 ? 8 : 7) * blk(nb * (int64_t)ns[l] * ns[l] * ns[l], w);
+            for (size_t l = 1; l < ns.size(); ++l) {
+                const int64_t m = nb * (int64_t)ns[l] * ns[l] * ns[l];
+                // FP64: operator (4), vectors b, x, y (and w on level 1), FP32 operator (4);
+                // FP32: vectors only
+                t += prec == 0 ? (l == 1 ? 8 : 7) * blk(m, 8) + 4 * blk(m, 4) : (l == 1 ? 4 : 3) * blk(m, 4);
+            }
             t += 3 * blk(nb * n3, w);   // cycle output, second residual and direction on level 0
         }
     }

@@ -3,7 +3,7 @@
 One V-cycle applied through the C ABI (STOKES_OP_MG_SHAT, STOKES_OP_MG_A) is
 compared element by element with an independent scipy model of the same
 cycle, built from the oracle's assembled matrices: 2x2x2 aggregation with
-Galerkin coarse operators, damped Jacobi (0.9) on level 0 and on the coarse
+Galerkin coarse operators (formed in FP64, stored in FP32), damped Jacobi (0.9) on level 0 and on the coarse
 levels with a side of 64 or more, red-black Gauss-Seidel (red then black
 going down, black then red going up) on the smaller coarse levels, 8
 damped-Jacobi sweeps from zero on the coarsest level, the coarse correction
@@ -69,12 +69,19 @@ def black(n):
 
 
 def hierarchy(A0, ns):
-    """[(side, A, 1/D)] over the full grids of the levels, and the aggregations."""
+    """[(side, A, 1/D)] over the full grids of the levels, and the aggregations.
+    Each coarse level's Galerkin product is formed in FP64 from the level above
+    and stored rounded to FP32 (the cycle's arithmetic stays FP64), as the
+    library does."""
     levels, Ps = [], []
     A = A0.tocsr()
     for l, n in enumerate(ns):
-        d = A.diagonal()
-        levels.append((n, A, np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)))
+        Ar = A
+        if l >= 1:
+            Ar = A.copy()
+            Ar.data = Ar.data.astype(np.float32).astype(np.float64)
+        d = Ar.diagonal()
+        levels.append((n, Ar, np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)))
         if l + 1 < len(ns):
             Pm = aggregation(n)
             Ps.append(Pm)
