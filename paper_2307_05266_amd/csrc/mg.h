@@ -1308,6 +1308,29 @@ __global__ void k_mg_coarsest(MgGrid g, MgOp op, const T* __restrict__ b, T* __r
     for (int I = threadIdx.x; I < n; I += kMgCoarsestThreads) xout[I] = xs[cur][I];
 }
 
+// Per-block partials of (a, b), (a, c), (b, b) over n values, written as
+// part[3 * block + q] (the power iteration of the two-visit estimate; plain
+// contexts only)
+__global__ void __launch_bounds__(kBlock) k_dots3_flat(int n, const double* __restrict__ a,
+                                                       const double* __restrict__ b, const double* __restrict__ c,
+                                                       double* __restrict__ part) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int X = blockIdx.x * blockDim.x + threadIdx.x; X < n; X += gridDim.x * blockDim.x) {
+        const double av = a[X], bv = b[X];
+        v[0] += av * bv;
+        v[1] += av * c[X];
+        v[2] += bv * bv;
+    }
+    block_sum_all<3>(v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = v[q];
+}
+
+// out = s * in, flat
+__global__ void k_scale_flat(int n, const double* __restrict__ in, double s, double* __restrict__ out) {
+    for (int X = blockIdx.x * blockDim.x + threadIdx.x; X < n; X += gridDim.x * blockDim.x) out[X] = s * in[X];
+}
+
 // out = (float) in, flat
 __global__ void k_narrow_flat(int n, const double* __restrict__ in, float* __restrict__ out, size_t bstride) {
     shift_nn((size_t)blockIdx.y * bstride, in, out);

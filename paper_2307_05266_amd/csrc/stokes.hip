@@ -886,43 +886,53 @@ constexpr int kMgTwoVisitPowerIts = 20;
 // 1.7 with two visits stays best, 5 707 against 6 106 inner iterations with 1.3).
 constexpr double kMgDeepFallback = 1.3;
 
-// Largest eigenvalue of B_1 A_1 with the current cycle, by power iteration.
+// Largest eigenvalue of B_1 A_1 with the current cycle, by power iteration
+// on the device (dot products as per-block partials added on the host in
+// block order).
 stokes_status estimate_level1_lambda(stokes_ctx* c, double* mu_out) {
     MgHier& h = c->mgS;
     *mu_out = 0.0;
     auto v1 = mg_view(h, 1, 0.0);
-    const size_t n1 = (size_t)h.grid[1].n3;
-    std::vector<double> D(n1), x(n1), ax(n1), y(n1);
-    HIP_TRY(hipMemcpyAsync(D.data(), v1.D, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemsetAsync(v1.x, 0, n1 * sizeof(double), c->stream));   // zero right-hand side of the residual
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    uint64_t seed = 0x9E3779B97F4A7C15ull;
-    for (size_t i = 0; i < n1; ++i) {
-        seed ^= seed << 13;
-        seed ^= seed >> 7;
-        seed ^= seed << 17;
-        x[i] = D[i] > 0.0 ? (double)(seed >> 11) * 0x1.0p-53 - 0.5 : 0.0;
+    const int n1 = h.grid[1].n3;
+    const int nbk = flat_blocks(n1, 1024);
+    {
+        // start: seeded uniform noise on the level's unknowns
+        std::vector<double> D((size_t)n1), x((size_t)n1);
+        HIP_TRY(hipMemcpyAsync(D.data(), v1.D, (size_t)n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        uint64_t seed = 0x9E3779B97F4A7C15ull;
+        for (int i = 0; i < n1; ++i) {
+            seed ^= seed << 13;
+            seed ^= seed >> 7;
+            seed ^= seed << 17;
+            x[i] = D[i] > 0.0 ? (double)(seed >> 11) * 0x1.0p-53 - 0.5 : 0.0;
+        }
+        HIP_TRY(hipMemcpyAsync(v1.w, x.data(), (size_t)n1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemsetAsync(v1.x, 0, (size_t)n1 * sizeof(double), c->stream));   // zero right-hand side
+        HIP_TRY(hipStreamSynchronize(c->stream));
     }
     double mu = 0.0;
     for (int it = 0; it < kMgTwoVisitPowerIts; ++it) {
-        HIP_TRY(hipMemcpyAsync(v1.w, x.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        mg_level1_residual<double>(c, h, v1.x, v1.w, v1.b, nullptr);   // b_1 = 0 - A_1 x
+        mg_level1_residual<double>(c, h, v1.x, v1.w, v1.b, nullptr);                 // b_1 = 0 - A_1 x
         ST_TRY(mg_coarse<double>(c, h, 1, (const double*)v1.b, false, nullptr));   // y_1 = B_1 b_1
-        HIP_TRY(hipMemcpyAsync(ax.data(), v1.b, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipMemcpyAsync(y.data(), v1.y, n1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        hipLaunchKernelGGL(k_dots3_flat, dim3(nbk), dim3(kBlock), 0, c->stream, n1, (const double*)v1.b,
+                           (const double*)v1.y, (const double*)v1.w, c->dpart);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(c->host_part, c->dpart, (size_t)3 * nbk * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         // signs cancel: (A x, B A x) / (A x, x) from b_1 = -A x and y_1 = -B A x
         double num = 0.0, den = 0.0, yy = 0.0;
-        for (size_t i = 0; i < n1; ++i) {
-            num += ax[i] * y[i];
-            den += ax[i] * x[i];
-            yy += y[i] * y[i];
+        for (int q = 0; q < nbk; ++q) {
+            num += c->host_part[3 * q];
+            den += c->host_part[3 * q + 1];
+            yy += c->host_part[3 * q + 2];
         }
         den = -den;
         if (!(den > 0.0) || !(yy > 0.0) || !std::isfinite(num)) return STOKES_OK;   // nothing to estimate
         mu = num / den;
-        const double sc = -1.0 / std::sqrt(yy);
-        for (size_t i = 0; i < n1; ++i) x[i] = y[i] * sc;
+        hipLaunchKernelGGL(k_scale_flat, dim3(nbk), dim3(kBlock), 0, c->stream, n1, (const double*)v1.y,
+                           -1.0 / std::sqrt(yy), v1.w);                              // next x = B A x / |B A x|
     }
     *mu_out = mu;
     return STOKES_OK;
