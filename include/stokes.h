@@ -72,8 +72,9 @@ typedef enum {
     STOKES_OP_DIAG_SHAT = 5,    /* -> cells: diag(B diag(A)^{-1} B^T) (input ignored) */
     STOKES_OP_PROJECT = 6,      /* cells -> cells: remove each component's mean */
     STOKES_OP_S = 7,            /* cells -> cells: B A^{-1} B^T p with an inner solve at eps_A */
-    STOKES_OP_MG_SHAT = 8,      /* cells -> cells: one V-cycle of the SIMPLE-matrix multigrid preconditioner
-                                   (STOKES_E_LIMIT when the geometry has no hierarchy) */
+    STOKES_OP_MG_SHAT = 8,      /* cells -> cells: one cycle of the SIMPLE-matrix multigrid preconditioner,
+                                   as the solves apply it (level 1 visited twice where option "mg_visits"
+                                   says so; STOKES_E_LIMIT when the geometry has no hierarchy) */
     STOKES_OP_MG_A = 9          /* faces -> faces: one V-cycle of the multigrid preconditioner of A (same) */
 } stokes_op;
 

@@ -388,19 +388,28 @@ __global__ void __launch_bounds__(kBlock) k_mgf_tiled(Sweep s, int cn, const uin
 // the plane that issued it.  A point's six face states come from its 16-bit
 // code (k_code2), so it needs neither the stored 1/D nor its neighbours'
 // codes: 1/D is recomputed with the arithmetic of k_inv_diag_Shat (bitwise the
-// stored value).  Same arithmetic as the unpipelined kernel, point by point.
+// stored value), and the six face weights it needs are kept for the point's
+// stencil.  Same arithmetic as the unpipelined kernel, point by point.
+// The six face weights of a voxel (lower x, y, z, then upper x, y, z) from its
+// 16-bit code, and its inverse diagonal.
 template <class T>
-__device__ __forceinline__ T inv_dS_of(int c2, const FaceTab<T>& ft) {
+__device__ __forceinline__ T weights_S2(int c2, const FaceTab<T>& ft, T (&w)[6]) {
     const int lo = c2 & 255, up = c2 >> 8;
-    const T dS = ((ft.inv[0][lo] + ft.inv[0][up]) + (ft.inv[1][lo] + ft.inv[1][up])) + (ft.inv[2][lo] + ft.inv[2][up]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w[a] = ft.inv[a][lo];
+        w[3 + a] = ft.inv[a][up];
+    }
+    const T dS = ((w[0] + w[3]) + (w[1] + w[4])) + (w[2] + w[5]);
     return dS > T(0) ? T(1) / dS : T(0);
 }
 
-// the SIMPLE matrix at level 0 from a point's 16-bit code (lower and upper faces)
+// the SIMPLE matrix at level 0 from a voxel's six face weights (the sums of
+// mgf_apply<T, kMgFineShat> in the same order)
 template <class T>
-__device__ __forceinline__ T mgf_apply_S2(const T (&v)[7], int c2, const FaceTab<T>& ft) {
-    const int lo = c2 & 255, up = c2 >> 8;
-    return mgf_apply<T, kMgFineShat>(v, lo, up, up, up, 0, ft);
+__device__ __forceinline__ T apply_S_w(const T (&v)[7], const T (&w)[6]) {
+    return ((w[0] * (v[0] - v[1]) + w[3] * (v[0] - v[2])) + (w[1] * (v[0] - v[3]) + w[4] * (v[0] - v[4]))) +
+           (w[2] * (v[0] - v[5]) + w[5] * (v[0] - v[6]));
 }
 
 template <class T>
@@ -421,7 +430,7 @@ __device__ __forceinline__ void mgfs_load(MgfRawS<T>& q, int N, int cn, int i, i
 
 template <class T>
 struct MgfPtS {
-    int cd;
+    T w[6];         // face weights (weights_S2)
     T inv, b, x;
 };
 
@@ -444,8 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, c
     const FaceTab<T>& ftr = ft;
     auto finish = [scale, omega, &ftr](const MgfRawS<T>& q) {
         MgfPtS<T> p;
-        p.cd = q.cd;
-        p.inv = inv_dS_of<T>(q.cd, ftr);
+        p.inv = weights_S2<T>(q.cd, ftr, p.w);
         p.b = q.b;
         p.x = omega * p.inv * q.b;
         if (p.inv > T(0)) p.x += scale * q.e;
@@ -477,7 +485,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_smooth_S_pipe(Sweep s, int cn, c
         __syncthreads();
         const T* tl = tile[buf];
         const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
-        const T ax = mgf_apply_S2<T>(v, cur.cd, ft);
+        const T ax = apply_S_w<T>(v, cur.w);
         const T yv = cur.inv > T(0) ? v[0] + omega * cur.inv * (cur.b - ax) : T(0);
         if (tt.valid) {
             out[wi + N * (wj + N * k)] = yv;
@@ -682,8 +690,7 @@ __device__ __forceinline__ void mgfu_load(MgfRawU<T>& w, int X, const uint16_t* 
 template <class T>
 __device__ __forceinline__ MgfPtS<T> mgfu_finish(const MgfRawU<T>& w, T alpha, T omega, const FaceTab<T>& ft) {
     MgfPtS<T> p;
-    p.cd = w.cd;
-    p.inv = inv_dS_of<T>(w.cd, ft);
+    p.inv = weights_S2<T>(w.cd, ft, p.w);
     p.b = w.r - alpha * w.q;
     p.x = omega * p.inv * p.b;
     return p;
@@ -745,7 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_mgf_update_restrict_S_pipe(Sweep s, 
         __syncthreads();
         const T* tl = tile[buf];
         const T v[7] = {cur.x, tl[own - 1], tl[own + 1], tl[own - W], tl[own + W], xprev, nxt.x};
-        rsum += cur.b - mgf_apply_S2<T>(v, cur.cd, ft);
+        rsum += cur.b - apply_S_w<T>(v, cur.w);
         if (k & 1) {
             const int cN = N >> 1;
             T rs[1] = {rsum};
