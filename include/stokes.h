@@ -283,7 +283,8 @@ stokes_status stokes_set_stream(stokes_ctx *ctx, void *hip_stream);
  *                 has a side of at least 64, is not the coarsest and runs damped
  *                 Jacobi ("mg_coarse_gs" not 2).  0 (default): two visits on
  *                 plain contexts whose level 1 has a side of at least 128, if a
- *                 power iteration at the first solve (20 products B_1 A_1 x)
+ *                 power iteration at the first SIMPLE-preconditioned solve (or
+ *                 STOKES_OP_MG_SHAT application; 20 products B_1 A_1 x)
  *                 puts the largest eigenvalue below 1.8 -- when it does not and
  *                 "mg_scale_deep" is unset, it retries with the corrections
  *                 below level 1 scaled by 1.3 and keeps that scale if the

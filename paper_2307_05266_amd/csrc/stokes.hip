@@ -2195,7 +2195,7 @@ stokes_status stokes_solve(stokes_ctx* c, stokes_precond precond, double tol, st
     if (!c) return STOKES_E_ARG;
     if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
     if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
-    ST_TRY(prepare_two_visits(c));
+    if (precond == STOKES_SIMPLE) ST_TRY(prepare_two_visits(c));   // the SIMPLE preconditioner's cycle only
     const auto t0 = std::chrono::steady_clock::now();
     c->t_solve0 = t0;
     stokes_status st;
@@ -2222,7 +2222,7 @@ stokes_status stokes_solve_rhs(stokes_ctx* c, stokes_precond precond, double tol
     if (precond != STOKES_UZAWA && precond != STOKES_SIMPLE) return STOKES_E_ARG;
     if (!(tol > 0.0) || !std::isfinite(tol)) return STOKES_E_ARG;
     if (c->batch_api || c->precision != 0) return STOKES_E_STATE;
-    ST_TRY(prepare_two_visits(c));
+    if (precond == STOKES_SIMPLE) ST_TRY(prepare_two_visits(c));
     const auto t0 = std::chrono::steady_clock::now();
     c->t_solve0 = t0;
     stokes_status st;
