@@ -76,6 +76,8 @@ def test_tight_spheres_256_mixed_and_fp64(P):
         say(f"    fp64  k={r64['k_hat']:.14e} outer={r64['outer_iters']} t={r64['seconds']:.1f}s")
         assert r64["status"] == 0
         check_solution(s, r64, light, rng)
+    # level 1 (128^3) is visited twice by the SIMPLE matrix's cycle (estimate 1.62 < 1.8)
+    assert rm["flags"] & P.STOKES_FLAG_MG_TWO_VISITS and r64["flags"] & P.STOKES_FLAG_MG_TWO_VISITS
     assert abs(rm["k_hat"] - r64["k_hat"]) <= 1e-4 * r64["k_hat"]
     assert abs(rm["outer_iters"] - r64["outer_iters"]) <= 10
 
@@ -95,6 +97,8 @@ def test_spheres_224_partial_coarse_tiles(P):
         s.set_option("precision", 0)
         r64 = s.solve(P.STOKES_SIMPLE, TOL)
         assert r64["status"] == 0
+    # level 1 (112^3) is below the two-visit side: one visit
+    assert not (r["flags"] & P.STOKES_FLAG_MG_TWO_VISITS)
     assert abs(r["k_hat"] - r64["k_hat"]) <= 1e-4 * r64["k_hat"]
 
 
@@ -107,4 +111,7 @@ def test_grf_512_mixed(P):
         r = s.solve(P.STOKES_SIMPLE, TOL)
         say(f"    mixed k={r['k_hat']:.14e} outer={r['outer_iters']} t={r['seconds']:.1f}s")
         assert r["status"] == 0
+        # two visits of level 1, with the corrections below it scaled 1.3 (the estimate
+        # with 1.7 is 3.29, with 1.3 1.64)
+        assert r["flags"] & P.STOKES_FLAG_MG_TWO_VISITS
         check_solution(s, r, light, np.random.default_rng(6))
