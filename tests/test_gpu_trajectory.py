@@ -157,6 +157,33 @@ def test_trajectory_64_against_stored_oracle(P, idx):
     assert n >= 10
 
 
+def test_trajectory_128_against_stored_oracle(P):
+    """128^3 sphere pack r=6 porosity 0.5 (the benchmark-size pack; four multigrid
+    levels, one visit of level 1): outer count, k_hat and the CG coefficients up
+    to the rounding horizon against the oracle's trajectory stored by
+    tests/golden/make_oracle_trajectories.py --size 128 (the oracle needs about
+    forty minutes per solve there)."""
+    import hashlib
+    with open(os.path.join(HERE, "golden", "oracle_trajectories_128.json")) as f:
+        case = json.load(f)["cases"][0]
+    m = spheres(128, 6.0, 0.5, 0)
+    assert hashlib.sha256(np.ascontiguousarray(m).tobytes()).hexdigest()[:16] == case["mask_sha256_16"]
+    with P.Stokes(m, (1.0, 0.0, 0.0)) as s:
+        info = s.info()
+        rep = s.solve(P.STOKES_SIMPLE, 1e-8)
+        hist = s.history()
+    say(f"[trajectory 128] {case['name']} {case['precond']}: outer gpu {rep['outer_iters']} oracle "
+        f"{case['outer_iters']} horizon {case['horizon']} k gpu {rep['k_hat']:.14e} oracle {case['k_hat']:.14e}")
+    assert info["mg_levels_S"] == 4 and info["mg_levels_A"] == 4
+    assert rep["status"] == 0
+    assert abs(rep["outer_iters"] - case["outer_iters"]) <= 1
+    assert rep["k_hat"] == pytest.approx(case["k_hat"], rel=1e-6)
+    check_report_ritz(rep, hist)
+    n = check_prefix(hist, np.array(case["alpha"]), np.array(case["beta"]), np.array(case["k_col"]),
+                     case["horizon"])
+    assert n >= 10
+
+
 def test_S_operator_hook_against_oracle(P):
     """STOKES_OP_S (B A^-1 B^T p with an inner solve at eps_A) against the oracle's
     B, B^T and inner A solve, on a multi-component geometry."""
