@@ -875,8 +875,10 @@ stokes_status vcycle(stokes_ctx* c, MgHier& h, const T* b0, const T* invd0, T* z
 // level 1 (CPU model, random-field packs: 1.40 with three levels below level 1,
 // 1.73 with four).  So in the auto mode the largest mu is estimated once per
 // context (again after a multigrid option changes) by power iteration on the
-// device with host dot products, and two visits are used only below
-// kMgTwoVisitMaxLambda.  Plain contexts only (batched ones keep one visit).
+// device, and two visits are used only below kMgTwoVisitMaxLambda: a power
+// iteration approaches the largest eigenvalue from below, so the bound keeps a
+// margin under 2 (at 1.8 the top of the spectrum already maps to 0.36).  Plain
+// contexts only (batched ones keep one visit).
 constexpr double kMgTwoVisitMaxLambda = 1.8;
 constexpr int kMgTwoVisitPowerIts = 20;
 // Fallback scale of the corrections below level 1 when the estimate with the
